@@ -1,0 +1,493 @@
+/*
+ * CPU FP64 oracle for the time-sliced periodic retarded-time field.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, by the build check, by the smoke
+ * check and by the CPU baseline leg of the benchmark. The HIP library never
+ * links, includes or calls anything here, and nothing here uses the library.
+ *
+ * What is computed (Sec. 2.1 Eqs. 9-10, Sec. 2.2 Eq. 11 and algorithm
+ * steps 2 and 6):
+ *
+ *   J_b(x) = sum_k sum_c G_{k,b}((x - c) mod N) * S_k(c)
+ *
+ *   G_{k,b}(c) = (1/m^3) sum_{subpoints a} sum_{images u}
+ *                [T_k <= n < T_{k+1}] * pref * phi_b(rho) / (4 pi rho^2)
+ *
+ * with rho^2 = n h^2, h = L/(2 m N), and n the exact integer
+ *   n = sum_d (2m (c_d + u_d N) + o_{a_d})^2,  o_a = 2a + 1 - m,
+ * T_k = (r_k/h)*(r_k/h) in IEEE double (half-open shells [r_k, r_{k+1})).
+ * When r_0 = 0 the self pair (c = 0, u = 0) is replaced by the exact cube
+ * average of pref*phi/(4 pi r^2), which is finite.
+ *
+ * Every loop here is the plain definition: a sum over cells, images and
+ * subpoints; a naive separable DFT; an O(N^6) brute force. Nothing is
+ * blocked or reordered beyond skipping images that lie entirely outside the
+ * shells (the paper's "effective horizon", algorithm step 2).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t kind;   /* 0: phi=1; 1: max(0, a e^{-(r/s)^p} - c); 2: Eq. 15 hard cut */
+    int32_t pad_;
+    double a, s, p, c, cut, prefactor;
+} or_atten;
+
+static const double OR_PI = 3.141592653589793238462643383279502884;
+
+/* ---- radial factor (Eq. 15 and its continuous variant) ----------------- */
+
+double or_phi(const or_atten *at, double r)
+{
+    if (at->kind == 0) return 1.0;
+    double v = at->a * exp(-pow(r / at->s, at->p)) - at->c;
+    if (at->kind == 1) return v > 0.0 ? v : 0.0;
+    return (r <= at->cut) ? v : 0.0;
+}
+
+/* Upper end of the support of phi (where the integrand stops). */
+static double phi_support_end(const or_atten *at)
+{
+    if (at->kind == 0) return INFINITY;
+    if (at->kind == 2) return at->cut;
+    if (at->c <= 0.0) return INFINITY;
+    if (at->a <= at->c) return 0.0;
+    return at->s * pow(log(at->a / at->c), 1.0 / at->p);
+}
+
+/* Tanh-sinh quadrature of a e^{-(r/s)^p} - c over [0, U]. The r^p cusp at
+ * r = 0 is an endpoint singularity, which this rule handles. Step halving
+ * until two levels agree to 1e-16 relative. */
+static double smooth_part(const or_atten *at, double r)
+{
+    return at->a * exp(-pow(r / at->s, at->p)) - at->c;
+}
+
+static double tanh_sinh_0U(const or_atten *at, double U)
+{
+    if (U <= 0.0) return 0.0;
+    double prev = 0.0;
+    for (int level = 3; level <= 12; ++level) {
+        double hstep = ldexp(1.0, -level);
+        double sum = 0.0;
+        for (int i = -(int)(4.0 / hstep); i <= (int)(4.0 / hstep); ++i) {
+            double t = i * hstep;
+            double u = 0.5 * OR_PI * sinh(t);
+            /* r = U (1 + tanh u) / 2 = U / (1 + e^{-2u}) */
+            double r = U / (1.0 + exp(-2.0 * u));
+            double ch = cosh(u);
+            double w = 0.5 * OR_PI * cosh(t) / (ch * ch);
+            if (!(r > 0.0) || r >= U || w == 0.0) continue;
+            sum += w * smooth_part(at, r);
+        }
+        double est = 0.5 * U * hstep * sum;
+        if (level > 3 && fabs(est - prev) <= 1e-15 * fabs(est)) return est;
+        prev = est;
+    }
+    return prev;
+}
+
+/* Phi(R) = int_0^R phi(r) dr */
+double or_Phi(const or_atten *at, double R)
+{
+    if (R <= 0.0) return 0.0;
+    if (at->kind == 0) return R;
+    double U = R;
+    double e = phi_support_end(at);
+    if (U > e) U = e;
+    return tanh_sinh_0U(at, U);
+}
+
+/* Shell integral of phi over [r0, r1). */
+double or_shell_integral(const or_atten *at, double r0, double r1)
+{
+    return or_Phi(at, r1) - or_Phi(at, r0);
+}
+
+/* Gauss-Legendre nodes/weights on [-1,1] by Newton iteration on P_n. */
+static void gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = cos(OR_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1; p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1; p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = -z; x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Cube average of pref * phi(r) / (4 pi r^2) over the cell [-l/2, l/2]^3.
+ * Splitting the cube into six pyramids with apex at the centre, each face
+ * contributes int int (l/2) Phi(R) / (4 pi R^3) dy dz with
+ * R = sqrt(l^2/4 + y^2 + z^2); the average is 6/l^3 times one face. The
+ * face integrand is smooth (R >= l/2), so a tensor Gauss-Legendre rule on
+ * the quarter face [0, l/2]^2 (times 4) converges fast. */
+double or_self_cell(const or_atten *at, double l)
+{
+    enum { NG = 48 };
+    double gx[NG], gw[NG];
+    gauss_legendre(NG, gx, gw);
+    double hl = 0.5 * l;
+    double acc = 0.0;
+    for (int i = 0; i < NG; ++i) {
+        double y = 0.5 * hl * (gx[i] + 1.0);
+        for (int j = 0; j < NG; ++j) {
+            double z = 0.5 * hl * (gx[j] + 1.0);
+            double R = sqrt(hl * hl + y * y + z * z);
+            acc += gw[i] * gw[j] * hl * or_Phi(at, R) / (R * R * R);
+        }
+    }
+    acc *= 0.25 * hl * hl;                  /* Jacobian of [-1,1]^2 -> [0,l/2]^2 */
+    double face = 4.0 * acc / (4.0 * OR_PI); /* whole face */
+    return at->prefactor * 6.0 * face / (l * l * l);
+}
+
+/* ---- shell kernel (Eq. 10, algorithm step 2) --------------------------- */
+
+typedef struct {
+    int N, K, m;
+    double L, l, h;
+    const double *radii;
+    double T[1025];        /* thresholds T_k = (r_k/h)^2, K+1 entries */
+    double rmin, rmax;     /* r_0, r_K */
+    int U;                 /* image range |u_d| <= U */
+    double self_val;       /* cube average for the self pair when r_0 == 0 */
+    or_atten at;
+} kern_t;
+
+static int kern_init(kern_t *kp, int N, double L, int K, const double *radii,
+                     int m, const or_atten *at)
+{
+    if (K < 1 || K > 1024) return -1;
+    kp->N = N; kp->K = K; kp->m = m; kp->L = L;
+    kp->l = L / N;
+    kp->h = L / (2.0 * m * N);
+    kp->radii = radii;
+    for (int k = 0; k <= K; ++k) {
+        double q = radii[k] / kp->h;
+        kp->T[k] = q * q;
+    }
+    kp->rmin = radii[0];
+    kp->rmax = radii[K];
+    kp->U = (int)ceil(radii[K] / L) + 1;
+    kp->at = *at;
+    kp->self_val = (radii[0] == 0.0) ? or_self_cell(at, kp->l) : 0.0;
+    return 0;
+}
+
+/* Value of one subpoint at squared half-subcell distance n. */
+static double point_value(const kern_t *kp, int64_t n)
+{
+    double rho = sqrt((double)n) * kp->h;
+    return kp->at.prefactor * or_phi(&kp->at, rho) /
+           (4.0 * OR_PI * rho * rho) / ((double)kp->m * kp->m * kp->m);
+}
+
+/* Shell index of n, or -1 when outside [T_0, T_K). */
+static int shell_of(const kern_t *kp, int64_t n)
+{
+    double dn = (double)n;
+    if (dn < kp->T[0] || dn >= kp->T[kp->K]) return -1;
+    int lo = 0, hi = kp->K;            /* T[lo] <= dn < T[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (kp->T[mid] <= dn) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+/* Add the contributions of displacement d = (d0,d1,d2) (cell units, any
+ * integers) to out[k0..k1) (absolute shell indices; out is indexed by k-k0).
+ * Self pair handled when d == 0 mod N and r_0 == 0. */
+static void kern_accumulate(const kern_t *kp, int d0, int d1, int d2,
+                            int k0, int k1, double *out)
+{
+    const int N = kp->N, m = kp->m, U = kp->U;
+    const double l = kp->l;
+    int dd[3] = { ((d0 % N) + N) % N, ((d1 % N) + N) % N, ((d2 % N) + N) % N };
+    const double lo_r = kp->radii[k0], hi_r = kp->radii[k1];
+    for (int u0 = -U; u0 <= U; ++u0)
+    for (int u1 = -U; u1 <= U; ++u1)
+    for (int u2 = -U; u2 <= U; ++u2) {
+        int64_t cx[3] = { dd[0] + (int64_t)u0 * N, dd[1] + (int64_t)u1 * N,
+                          dd[2] + (int64_t)u2 * N };
+        /* bounding test on the whole cell [c - l/2, c + l/2]^3 */
+        double mn2 = 0.0, mx2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double c = (double)cx[a] * l;
+            double lo = c - 0.5 * l, hi = c + 0.5 * l;
+            double near = (lo > 0.0) ? lo : ((hi < 0.0) ? -hi : 0.0);
+            double far = fmax(fabs(lo), fabs(hi));
+            mn2 += near * near; mx2 += far * far;
+        }
+        double margin = 1e-9 * (hi_r + l);
+        if (sqrt(mn2) > hi_r + margin) continue;
+        if (sqrt(mx2) < lo_r - margin) continue;
+        if (kp->rmin == 0.0 && cx[0] == 0 && cx[1] == 0 && cx[2] == 0) {
+            if (k0 == 0) out[0] += kp->self_val;
+            continue;
+        }
+        for (int a0 = 0; a0 < m; ++a0)
+        for (int a1 = 0; a1 < m; ++a1)
+        for (int a2 = 0; a2 < m; ++a2) {
+            int64_t q0 = 2 * m * cx[0] + (2 * a0 + 1 - m);
+            int64_t q1 = 2 * m * cx[1] + (2 * a1 + 1 - m);
+            int64_t q2 = 2 * m * cx[2] + (2 * a2 + 1 - m);
+            int64_t n = q0 * q0 + q1 * q1 + q2 * q2;
+            int k = shell_of(kp, n);
+            if (k < k0 || k >= k1) continue;
+            out[k - k0] += point_value(kp, n);
+        }
+    }
+}
+
+/* All K shell values at displacement (d0,d1,d2). */
+int or_G_at(int N, double L, int K, const double *radii, int m,
+            const or_atten *at, int d0, int d1, int d2, double *outK)
+{
+    kern_t kp;
+    if (kern_init(&kp, N, L, K, radii, m, at)) return -1;
+    memset(outK, 0, sizeof(double) * K);
+    kern_accumulate(&kp, d0, d1, d2, 0, K, outK);
+    return 0;
+}
+
+/* Dense kernel G[k][i][j][kx] for all K shells over the full N^3 grid.
+ * If conserve != 0, each shell is rescaled so that l^3 sum_c G_k(c) equals
+ * the shell integral of phi. */
+int or_build_G(int N, double L, int K, const double *radii, int m,
+               const or_atten *at, int conserve, double *G)
+{
+    kern_t kp;
+    if (kern_init(&kp, N, L, K, radii, m, at)) return -1;
+    const int64_t n3 = (int64_t)N * N * N;
+    memset(G, 0, sizeof(double) * n3 * K);
+    #pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * K);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t c = 0; c < n3; ++c) {
+            int i = (int)(c / ((int64_t)N * N)), j = (int)((c / N) % N), x = (int)(c % N);
+            memset(tmp, 0, sizeof(double) * K);
+            kern_accumulate(&kp, i, j, x, 0, K, tmp);
+            for (int k = 0; k < K; ++k) G[(int64_t)k * n3 + c] = tmp[k];
+        }
+        free(tmp);
+    }
+    if (conserve) {
+        double l3 = kp.l * kp.l * kp.l;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0, comp = 0.0;
+            for (int64_t c = 0; c < n3; ++c) {      /* Neumaier sum */
+                double v = G[(int64_t)k * n3 + c], t = s + v;
+                comp += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
+                s = t;
+            }
+            s += comp;
+            double target = or_shell_integral(at, radii[k], radii[k + 1]);
+            double f = (s != 0.0) ? target / (l3 * s) : 0.0;
+            for (int64_t c = 0; c < n3; ++c) G[(int64_t)k * n3 + c] *= f;
+        }
+    }
+    return 0;
+}
+
+/* ---- route D: direct real-space periodic summation (Eq. 11 summed over
+ * slices, algorithm step 6) --------------------------------------------- */
+
+/* Neumaier compensated accumulator */
+typedef struct { double s, c; } nsum;
+static inline void nadd(nsum *a, double v)
+{
+    double t = a->s + v;
+    a->c += (fabs(a->s) >= fabs(v)) ? (a->s - t) + v : (v - t) + a->s;
+    a->s = t;
+}
+
+/* Dense-kernel version: G is K x N^3 for one band; sources of slice k are
+ * src_cell[off[k] .. off[k+1]), src_lum likewise. */
+int or_field_direct(int N, int K, const double *G,
+                    const int64_t *off, const int64_t *src_cell, const double *src_lum,
+                    int64_t n_targets, const int64_t *targets, double *J)
+{
+    const int64_t n3 = (int64_t)N * N * N;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_targets; ++t) {
+        int64_t x = targets[t];
+        int xi = (int)(x / ((int64_t)N * N)), xj = (int)((x / N) % N), xk = (int)(x % N);
+        nsum acc = { 0.0, 0.0 };
+        for (int k = 0; k < K; ++k) {
+            const double *Gk = G + (int64_t)k * n3;
+            for (int64_t s = off[k]; s < off[k + 1]; ++s) {
+                int64_t c = src_cell[s];
+                int ci = (int)(c / ((int64_t)N * N)), cj = (int)((c / N) % N), ck = (int)(c % N);
+                int di = (xi - ci + N) % N, dj = (xj - cj + N) % N, dk = (xk - ck + N) % N;
+                nadd(&acc, src_lum[s] * Gk[((int64_t)di * N + dj) * N + dk]);
+            }
+        }
+        J[t] = acc.s + acc.c;
+    }
+    return 0;
+}
+
+/* Kernel-on-demand version for grids whose dense kernel does not fit: each
+ * (target, source) pair evaluates only the shell of the source's slice. */
+int or_field_direct_ondemand(int N, double L, int K, const double *radii, int m,
+                             const or_atten *at,
+                             const int64_t *off, const int64_t *src_cell, const double *src_lum,
+                             int64_t n_targets, const int64_t *targets, double *J)
+{
+    kern_t kp;
+    if (kern_init(&kp, N, L, K, radii, m, at)) return -1;
+    /* Cheap reject: a displacement whose minimum-image distance exceeds r_K
+     * plus a cell diagonal, and r_K < L/2 - l, has no image in any shell. */
+    const double diag = sqrt(3.0) * kp.l;
+    const int single_image = (radii[K] + diag < 0.5 * L - diag);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_targets; ++t) {
+        int64_t x = targets[t];
+        int xi = (int)(x / ((int64_t)N * N)), xj = (int)((x / N) % N), xk = (int)(x % N);
+        nsum acc = { 0.0, 0.0 };
+        for (int k = 0; k < K; ++k) {
+            double lo = radii[k] - diag, hi = radii[k + 1] + diag;
+            for (int64_t s = off[k]; s < off[k + 1]; ++s) {
+                int64_t c = src_cell[s];
+                int ci = (int)(c / ((int64_t)N * N)), cj = (int)((c / N) % N), ck = (int)(c % N);
+                int d[3] = { (xi - ci + N) % N, (xj - cj + N) % N, (xk - ck + N) % N };
+                if (single_image) {
+                    double r2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        int e = d[a] > N / 2 ? N - d[a] : d[a];
+                        r2 += (double)e * e;
+                    }
+                    double r = sqrt(r2) * kp.l;
+                    if (r > hi || r < lo) continue;
+                }
+                double g = 0.0;
+                kern_accumulate(&kp, d[0], d[1], d[2], k, k + 1, &g);
+                if (g != 0.0) nadd(&acc, src_lum[s] * g);
+            }
+        }
+        J[t] = acc.s + acc.c;
+    }
+    return 0;
+}
+
+/* ---- naive DFT (Eq. 12 convention) ------------------------------------- */
+
+/* Twiddle table e^{sign 2 pi i j / N}, j in [0, N), from long double libm. */
+static void twiddles(int N, int sign, double complex *w)
+{
+    for (int j = 0; j < N; ++j) {
+        long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)N;
+        w[j] = (double)cosl(ang) + (double)(sign * sinl(ang)) * I;
+    }
+}
+
+/* In-place separable naive DFT of a complex N^3 array along all three axes.
+ * sign = -1: forward (unnormalised); +1: inverse (unnormalised). */
+int or_dft3_naive(int N, int sign, double complex *a)
+{
+    double complex *w = (double complex *)malloc(sizeof(double complex) * N);
+    twiddles(N, sign, w);
+    const int64_t NN = (int64_t)N * N;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int64_t st = (ax == 0) ? NN : (ax == 1) ? N : 1;
+        #pragma omp parallel
+        {
+            double complex *line = (double complex *)malloc(sizeof(double complex) * N);
+            #pragma omp for schedule(static)
+            for (int64_t ln = 0; ln < NN; ++ln) {
+                /* the two coordinates other than ax */
+                int64_t hi = ln / N, lo = ln % N;
+                int64_t base = (ax == 0) ? hi * N + lo
+                             : (ax == 1) ? hi * NN + lo
+                                         : (hi * N + lo) * N;
+                for (int j = 0; j < N; ++j) line[j] = a[base + j * st];
+                for (int p = 0; p < N; ++p) {
+                    double complex acc = 0.0;
+                    for (int j = 0; j < N; ++j)
+                        acc += line[j] * w[((int64_t)j * p) % N];
+                    a[base + p * st] = acc;
+                }
+            }
+            free(line);
+        }
+    }
+    free(w);
+    return 0;
+}
+
+/* Brute-force non-separable 3D DFT, O(N^6). */
+int or_dft3_brute(int N, int sign, const double complex *in, double complex *out)
+{
+    double complex *w = (double complex *)malloc(sizeof(double complex) * N);
+    twiddles(N, sign, w);
+    const int64_t n3 = (int64_t)N * N * N;
+    #pragma omp parallel for schedule(static)
+    for (int64_t P = 0; P < n3; ++P) {
+        int p = (int)(P / ((int64_t)N * N)), q = (int)((P / N) % N), r = (int)(P % N);
+        double complex acc = 0.0;
+        for (int64_t c = 0; c < n3; ++c) {
+            int i = (int)(c / ((int64_t)N * N)), j = (int)((c / N) % N), k = (int)(c % N);
+            acc += in[c] * w[((int64_t)i * p + (int64_t)j * q + (int64_t)k * r) % N];
+        }
+        out[P] = acc;
+    }
+    free(w);
+    return 0;
+}
+
+/* Brute-force circular convolution, O(N^6): out(x) = sum_c G((x-c) mod N) S(c). */
+int or_conv3_brute(int N, const double *G, const double *S, double *out)
+{
+    const int64_t n3 = (int64_t)N * N * N;
+    #pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < n3; ++x) {
+        int xi = (int)(x / ((int64_t)N * N)), xj = (int)((x / N) % N), xk = (int)(x % N);
+        nsum acc = { 0.0, 0.0 };
+        for (int64_t c = 0; c < n3; ++c) {
+            if (S[c] == 0.0) continue;
+            int ci = (int)(c / ((int64_t)N * N)), cj = (int)((c / N) % N), ck = (int)(c % N);
+            int64_t d = ((int64_t)((xi - ci + N) % N) * N + (xj - cj + N) % N) * N + (xk - ck + N) % N;
+            nadd(&acc, G[d] * S[c]);
+        }
+        out[x] = acc.s + acc.c;
+    }
+    return 0;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
