@@ -1,0 +1,205 @@
+/*
+ * lc.h - time-sliced retarded-time (light-cone) radiation field on a
+ * periodic 3D grid, for AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every band b of every periodic box,
+ *
+ *     J_b = IDFT( sum_k  G^_{k,b} . DFT(S_k) ) / N^3
+ *
+ * which is the time-sliced field of Sec. 2.1 (Eqs. 9-10) discretised on a
+ * uniform grid (Sec. 2.2, Eq. 11) and evaluated by the convolution theorem
+ * (Eqs. 12-13, algorithm steps 2-6). S_k is the source grid of lookback
+ * slice k (luminosity per cell; the cell volume is absorbed, Eq. 11), and
+ * G_{k,b} the periodic retarded-time shell kernel of slice k (Eq. 10):
+ *
+ *   G_{k,b}(c) = (1/m^3) sum_{subpoints} sum_{images u}
+ *                [r_k <= rho < r_{k+1}] pref * phi_b(rho) / (4 pi rho^2)
+ *
+ * summed over the periodic images of a unit source (algorithm step 2) and
+ * averaged over m^3 subpoints of the cell (m = 1 is the paper's node rule).
+ * Membership is decided exactly: with h = L/(2 m N) a subpoint at integer
+ * half-subcell offsets q has n = q.q (an exact integer) and lies in slice k
+ * iff T_k <= n < T_{k+1}, T_k = (r_k/h)*(r_k/h) in IEEE double. When
+ * r_0 = 0 the unit source's own cell takes the exact cube average of
+ * pref * phi/(4 pi r^2), finite although the integrand is singular.
+ *
+ * DFT convention (Eq. 12): forward exp(-2 pi i (ip+jq+kr)/N), unnormalised;
+ * inverse exp(+...), scaled by 1/N^3.
+ *
+ * Grid layout: cell (i, j, k) at flat index (i*N + j)*N + k, k contiguous;
+ * its position is (i, j, k) * l with l = L/N (node convention, Sec. 2.2).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an lc_status (0 = success, < 0 = error); no
+ *     call throws or aborts. On error the plan is left unchanged and
+ *     lc_last_error() describes the failure.
+ *   - Arguments are validated on the host before any device work.
+ *   - All device work is enqueued on the plan's HIP stream; device pointers
+ *     passed in must stay valid and unmodified until the stream reaches the
+ *     call. Host-pointer sources are consumed before the call returns;
+ *     host-pointer outputs make lc_field synchronise the stream.
+ *   - The caller owns all memory passed in (workspace, sources, outputs).
+ *     The plan owns host tables only and sub-allocates inside the
+ *     caller's workspace; lc_destroy frees no caller memory.
+ *   - A plan is not thread-safe: use one host thread per plan.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LC_OK = 0,
+    LC_EINVAL = -1,        /* invalid argument or descriptor field */
+    LC_ENOMEM = -2,        /* workspace smaller than lc_workspace_bytes() */
+    LC_EDEVICE = -3,       /* no usable gfx950 device, or a HIP call failed */
+    LC_ESTATE = -4,        /* call out of order (e.g. field before kernels built) */
+    LC_EUNSUPPORTED = -5,  /* valid but unsupported size or combination */
+    LC_ENONFINITE = -6     /* non-finite value found in a source grid */
+} lc_status;
+
+/* Arithmetic of the transforms and the slice sum. */
+typedef enum {
+    /* FP64 everywhere; unfused passes (forward x, y, z per slice, then a
+     * separate multiply-accumulate over slices, then one inverse). */
+    LC_PREC_FP64 = 0,
+    /* FP32 everywhere, twiddles computed in FP32, plain FP32 slice sum,
+     * same unfused passes as LC_PREC_FP64. */
+    LC_PREC_FP32_PLAIN = 1,
+    /* FP32 butterflies with twiddles generated in FP64; the forward z
+     * transform, the multiply-accumulate over slices (compensated,
+     * Kahan) and the inverse z transform fused in one pass; the mean
+     * (DC) mode summed in FP64 and added back in FP64; kernels built in
+     * FP64 and stored in FP32. */
+    LC_PREC_FP32 = 2
+} lc_precision;
+
+typedef enum { LC_F32 = 0, LC_F64 = 1 } lc_dtype;
+typedef enum { LC_MEM_HOST = 0, LC_MEM_DEVICE = 1 } lc_mem;
+
+/* One periodic box. */
+typedef struct {
+    int32_t n;            /* grid side N: 8..1024, N = 2^a 3^b, N even    */
+    int32_t n_slices;     /* K >= 1 lookback slices (algorithm step 1)    */
+    int32_t n_bands;      /* B >= 1 radial factors sharing the sources    */
+    int32_t supersample;  /* m: 1 (node rule) .. 8 subpoints per axis     */
+    int32_t conserve;     /* 1: rescale G_{k,b} so l^3 sum_c G = shell
+                             integral of phi_b over [r_k, r_{k+1})         */
+    int32_t reserved;     /* must be 0                                    */
+    double box;           /* L, same length unit as radii                 */
+    const double *radii;  /* K+1 strictly increasing, r_0 >= 0 (host);
+                             slice k <-> shell [r_k, r_{k+1}), k = 0 the
+                             most recent (Eq. 9: tau - tau_{n+1} .. tau - tau_n) */
+} lc_box_desc;
+
+typedef struct {
+    int32_t n_boxes;              /* >= 1                                  */
+    int32_t precision;            /* lc_precision                          */
+    const lc_box_desc *boxes;     /* n_boxes entries (host)                */
+    void *hip_stream;             /* hipStream_t; NULL = default stream    */
+    void *workspace;              /* device memory, >= lc_workspace_bytes  */
+    size_t workspace_bytes;
+    int32_t use_graph;            /* 1: lc_step replays a captured graph   */
+    int32_t reserved;             /* must be 0                             */
+} lc_plan_desc;
+
+/* Radial factor phi_b (Eqs. 14-17). G = prefactor * phi / (4 pi r^2).
+ *   kind 0: phi = 1
+ *   kind 1: phi = max(0, a exp(-(r/s)^p) - c)            (continuous)
+ *   kind 2: phi = a exp(-(r/s)^p) - c if r <= cut else 0  (Eq. 15 as printed,
+ *           with s = 116.29 alpha and cut = 97.39 alpha)
+ * Requires a, s, p > 0 for kinds 1-2; prefactor finite. */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;             /* must be 0 */
+    double a, s, p, c, cut;
+    double prefactor;             /* 1.0 for the bare 1/(4 pi r^2) dilution */
+} lc_atten;
+
+/* Sources of one slice (Eq. 17's sum of point luminosities, deposited to
+ * the nearest grid point; several sources in a cell add).
+ *   kind 0: dense grid, `grid` holds N^3 values in the grid layout above.
+ *   kind 1: point list, n entries: cell[i] in [0, N^3) (flat index, int64),
+ *           lum[i] of type `dtype`. A device point list is deposited with
+ *           FP64 atomics (summation order of coincident sources varies).
+ * `dtype` gives the value type of grid / lum, `mem` where they live. */
+typedef struct {
+    int32_t kind;
+    int32_t dtype;                /* lc_dtype */
+    int32_t mem;                  /* lc_mem   */
+    int32_t reserved;             /* must be 0 */
+    const void *grid;
+    int64_t n;
+    const int64_t *cell;
+    const void *lum;
+} lc_sources;
+
+typedef struct lc_plan_s lc_plan_t;
+
+/* Bytes of device workspace the plan needs (0 on an invalid descriptor;
+ * the workspace fields of desc are ignored). Host only, no device call. */
+size_t lc_workspace_bytes(const lc_plan_desc *desc);
+
+/* Validate desc, carve the workspace, compute the FP64 host constants
+ * (thresholds T_k, twiddle tables, self-cell averages) and upload them.
+ * Errors: LC_EINVAL (bad field), LC_EUNSUPPORTED (N not 2^a 3^b in
+ * 8..1024, m > 8, or r_0 = 0 with r_1 < (sqrt(3)/2) l so that the self
+ * cell would straddle two slices), LC_ENOMEM (workspace too small or
+ * misaligned to 256 bytes), LC_EDEVICE (no gfx950 device). */
+int lc_plan(const lc_plan_desc *desc, lc_plan_t **out);
+
+/* Build G_{k,b} for all K slices of one (box, band) - algorithm steps 2-3:
+ * direct summation over images inside the shells (FP64), FP64 forward
+ * transform, real part of its non-redundant octant kept (G is real and
+ * even, so G^ is real and even). G^_{k,b}(0) is kept in FP64. Must be
+ * called for every (box, band) before lc_field / lc_step. Enqueued on the
+ * stream; uses the workspace's builder scratch. */
+int lc_build_greens(lc_plan_t *plan, int32_t box, int32_t band, const lc_atten *atten);
+
+/* Stage slice k of a box - algorithm step 4 up to the passes that do not
+ * depend on the kernel: deposit (point list) or read (dense grid), then the
+ * forward transform (x and y passes for LC_PREC_FP32, all three passes for
+ * the unfused forms). Replaces whatever the slice held; slices never
+ * pushed are zero. */
+int lc_push_sources(lc_plan_t *plan, int32_t box, int32_t slice, const lc_sources *src);
+
+/* Evaluate the field - algorithm steps 5-6 with the slice sum taken in
+ * spectral space (linearity; one inverse per band instead of one per
+ * slice). box = -1 selects all boxes, band = -1 all bands. out holds one
+ * pointer per selected (box, band), box-major, each to N^3 values of
+ * `dtype` in `mem`. Errors: LC_ESTATE if a selected kernel is not built. */
+int lc_field(lc_plan_t *plan, int32_t box, int32_t band, void *const *out,
+             int32_t dtype, int32_t mem);
+
+/* One whole step for every box: push all slices from srcs (box-major,
+ * sum_b K_b entries, device memory only) and evaluate every band into out
+ * (box-major, band, device memory). With use_graph = 1 the launch sequence
+ * is captured in a HIP graph on first use and replayed while the argument
+ * pointers are unchanged. */
+int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t dtype);
+
+/* Release the plan's host state (no caller memory is freed). NULL is a no-op. */
+void lc_destroy(lc_plan_t *plan);
+
+/* Text of the last error on the calling thread; valid until the next
+ * library call on this thread. Never NULL. */
+const char *lc_last_error(void);
+
+/* Largest |Im G^| / max|G^| seen by lc_build_greens for (box, band) (the
+ * kernel spectrum is real up to rounding); synchronises the stream. */
+int lc_greens_imag_ratio(lc_plan_t *plan, int32_t box, int32_t band, double *ratio);
+
+/* Copy G^_{k,b}(0) = sum_c G_{k,b}(c) (FP64) for all K slices to host
+ * memory dc[K]; synchronises the stream. */
+int lc_greens_dc(lc_plan_t *plan, int32_t box, int32_t band, double *dc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LC_H */

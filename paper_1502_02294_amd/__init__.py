@@ -1,0 +1,266 @@
+"""Python binding of the light-cone field library (include/lc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library liblc.so (built in-tree for gfx950). PyTorch supplies device
+memory (the workspace and the buffers) and the HIP stream. There is no CPU
+path: if the library is missing, loading fails with an error.
+
+The C entry points are exposed under their own names (lc_plan,
+lc_build_greens, lc_push_sources, lc_field, lc_step, lc_destroy,
+lc_last_error, lc_workspace_bytes); `Plan` wraps them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblc.so")
+
+LC_OK, LC_EINVAL, LC_ENOMEM, LC_EDEVICE, LC_ESTATE, LC_EUNSUPPORTED, LC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+LC_PREC_FP64, LC_PREC_FP32_PLAIN, LC_PREC_FP32 = 0, 1, 2
+LC_F32, LC_F64 = 0, 1
+LC_MEM_HOST, LC_MEM_DEVICE = 0, 1
+
+STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", -4: "LC_ESTATE",
+                -5: "LC_EUNSUPPORTED", -6: "LC_ENONFINITE"}
+
+EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_field",
+            "lc_step", "lc_destroy", "lc_last_error", "lc_greens_imag_ratio", "lc_greens_dc"]
+
+
+class lc_box_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_slices", C.c_int32), ("n_bands", C.c_int32),
+                ("supersample", C.c_int32), ("conserve", C.c_int32), ("reserved", C.c_int32),
+                ("box", C.c_double), ("radii", C.POINTER(C.c_double))]
+
+
+class lc_plan_desc(C.Structure):
+    _fields_ = [("n_boxes", C.c_int32), ("precision", C.c_int32),
+                ("boxes", C.POINTER(lc_box_desc)), ("hip_stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+
+
+class lc_atten(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a", C.c_double),
+                ("s", C.c_double), ("p", C.c_double), ("c", C.c_double), ("cut", C.c_double),
+                ("prefactor", C.c_double)]
+
+
+class lc_sources(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("mem", C.c_int32),
+                ("reserved", C.c_int32), ("grid", C.c_void_p), ("n", C.c_int64),
+                ("cell", C.c_void_p), ("lum", C.c_void_p)]
+
+
+class LCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load liblc.so. torch is imported first so that the library binds to
+    the same HIP runtime (same soname) as torch's device memory and streams."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime shared with torch)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    L.lc_workspace_bytes.argtypes = [C.POINTER(lc_plan_desc)]
+    L.lc_workspace_bytes.restype = C.c_size_t
+    L.lc_plan.argtypes = [C.POINTER(lc_plan_desc), C.POINTER(C.c_void_p)]
+    L.lc_build_greens.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_atten)]
+    L.lc_push_sources.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_sources)]
+    L.lc_field.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_int32]
+    L.lc_step.argtypes = [C.c_void_p, C.POINTER(lc_sources), C.POINTER(C.c_void_p), C.c_int32]
+    L.lc_destroy.argtypes = [C.c_void_p]
+    L.lc_destroy.restype = None
+    L.lc_last_error.restype = C.c_char_p
+    L.lc_greens_imag_ratio.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.lc_greens_dc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_field", "lc_step",
+                 "lc_greens_imag_ratio", "lc_greens_dc"]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def lc_last_error() -> str:
+    return load().lc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != LC_OK:
+        raise LCError(rc, lc_last_error())
+
+
+# ---- descriptor helpers -------------------------------------------------------------
+
+def make_box_desc(n: int, box: float, radii, n_bands: int = 1, supersample: int = 1,
+                  conserve: int = 0):
+    """Returns (desc, keepalive) with radii held in a ctypes double array."""
+    r = (C.c_double * len(radii))(*[float(v) for v in radii])
+    d = lc_box_desc(int(n), len(radii) - 1, int(n_bands), int(supersample), int(conserve), 0,
+                    float(box), C.cast(r, C.POINTER(C.c_double)))
+    return d, r
+
+
+def make_plan_desc(boxes: Sequence[lc_box_desc], precision: int, stream: int = 0,
+                   workspace: int = 0, workspace_bytes: int = 0, use_graph: int = 0):
+    arr = (lc_box_desc * len(boxes))(*boxes)
+    d = lc_plan_desc(len(boxes), int(precision), C.cast(arr, C.POINTER(lc_box_desc)),
+                     C.c_void_p(stream or None), C.c_void_p(workspace or None), int(workspace_bytes),
+                     int(use_graph), 0)
+    return d, arr
+
+
+def make_atten(at) -> lc_atten:
+    """From any object with kind, a, s, p, c, cut, prefactor attributes."""
+    return lc_atten(int(at.kind), 0, float(at.a), float(at.s), float(at.p), float(at.c),
+                    float(getattr(at, "cut", 0.0)), float(getattr(at, "prefactor", 1.0)))
+
+
+# ---- thin wrappers with the C names ---------------------------------------------------
+
+def lc_workspace_bytes(desc: lc_plan_desc) -> int:
+    return int(load().lc_workspace_bytes(C.byref(desc)))
+
+
+def lc_plan(desc: lc_plan_desc) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(load().lc_plan(C.byref(desc), C.byref(h)))
+    return h
+
+
+def lc_build_greens(plan, box: int, band: int, atten: lc_atten):
+    _check(load().lc_build_greens(plan, box, band, C.byref(atten)))
+
+
+def lc_push_sources(plan, box: int, slice_: int, src: lc_sources):
+    _check(load().lc_push_sources(plan, box, slice_, C.byref(src)))
+
+
+def lc_field(plan, box: int, band: int, outs: Sequence[int], dtype: int, mem: int):
+    arr = (C.c_void_p * len(outs))(*[C.c_void_p(o) for o in outs])
+    _check(load().lc_field(plan, box, band, arr, dtype, mem))
+
+
+def lc_step(plan, srcs: Sequence[lc_sources], outs: Sequence[int], dtype: int):
+    sarr = (lc_sources * len(srcs))(*srcs)
+    oarr = (C.c_void_p * len(outs))(*[C.c_void_p(o) for o in outs])
+    _check(load().lc_step(plan, sarr, oarr, dtype))
+
+
+def lc_destroy(plan):
+    load().lc_destroy(plan)
+
+
+# ---- torch-facing convenience ----------------------------------------------------------
+
+class Plan:
+    """A plan over one or more boxes, with its workspace in a torch uint8
+    tensor on the current device and work on the current torch stream.
+
+    boxes: sequence of objects with n, box, radii, bands (list), supersample,
+    conserve (e.g. lc_inputs.Box).
+    """
+
+    def __init__(self, boxes, precision: int = LC_PREC_FP64, use_graph: bool = False, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.precision = precision
+        self.boxes = list(boxes)
+        self._keep = []
+        descs = []
+        for b in self.boxes:
+            d, r = make_box_desc(b.n, b.box, b.radii, len(b.bands), b.supersample,
+                                 getattr(b, "conserve", 0))
+            descs.append(d)
+            self._keep.append(r)
+        probe, arr = make_plan_desc(descs, precision)
+        self._keep.append(arr)
+        nbytes = lc_workspace_bytes(probe)
+        if nbytes == 0:
+            raise LCError(LC_EINVAL, lc_last_error())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        desc, arr2 = make_plan_desc(descs, precision, self.stream.cuda_stream, aligned, nbytes,
+                                    1 if use_graph else 0)
+        self._keep.append(arr2)
+        self.handle = lc_plan(desc)
+
+    def build_greens(self, box: int = 0, band: int = 0, atten=None):
+        at = atten if atten is not None else self.boxes[box].bands[band]
+        lc_build_greens(self.handle, box, band, make_atten(at))
+
+    def build_all(self):
+        for bi, b in enumerate(self.boxes):
+            for band in range(len(b.bands)):
+                self.build_greens(bi, band)
+
+    def push_grid(self, box: int, slice_: int, grid):
+        """Dense source grid: a torch tensor (device or CPU) of N^3 float32/float64."""
+        t = grid.contiguous()
+        dt = LC_F64 if t.dtype == self.torch.float64 else LC_F32
+        if t.dtype not in (self.torch.float32, self.torch.float64):
+            raise TypeError("source grid must be float32 or float64")
+        mem = LC_MEM_DEVICE if t.is_cuda else LC_MEM_HOST
+        src = lc_sources(0, dt, mem, 0, t.data_ptr(), 0, None, None)
+        lc_push_sources(self.handle, box, slice_, src)
+        return t  # caller keeps it alive until the stream reaches the call
+
+    def push_points(self, box: int, slice_: int, cells, lum):
+        """Point list: int64 cells and float32/float64 luminosities (torch
+        tensors on one device)."""
+        c = cells.contiguous()
+        v = lum.contiguous()
+        dt = LC_F64 if v.dtype == self.torch.float64 else LC_F32
+        mem = LC_MEM_DEVICE if c.is_cuda else LC_MEM_HOST
+        src = lc_sources(1, dt, mem, 0, None, int(c.numel()), c.data_ptr() if c.numel() else None,
+                         v.data_ptr() if v.numel() else None)
+        lc_push_sources(self.handle, box, slice_, src)
+        return c, v
+
+    def field(self, box: int = 0, band: int = 0, dtype=None, out=None):
+        torch = self.torch
+        n = self.boxes[box].n
+        dtype = dtype or (torch.float64 if self.precision == LC_PREC_FP64 else torch.float32)
+        if out is None:
+            out = torch.empty((n, n, n), dtype=dtype, device=self.device)
+        dt = LC_F64 if out.dtype == torch.float64 else LC_F32
+        mem = LC_MEM_DEVICE if out.is_cuda else LC_MEM_HOST
+        lc_field(self.handle, box, band, [out.data_ptr()], dt, mem)
+        return out
+
+    def greens_dc(self, box: int = 0, band: int = 0):
+        K = len(self.boxes[box].radii) - 1
+        arr = (C.c_double * K)()
+        _check(load().lc_greens_dc(self.handle, box, band, arr))
+        return list(arr)
+
+    def greens_imag_ratio(self, box: int = 0, band: int = 0) -> float:
+        v = C.c_double()
+        _check(load().lc_greens_imag_ratio(self.handle, box, band, C.byref(v)))
+        return float(v.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

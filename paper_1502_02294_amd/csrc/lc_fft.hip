@@ -1,0 +1,286 @@
+// Forward/inverse x passes (real <-> half spectrum) and strided column
+// passes (y, z) of the 3D transform of Eq. 12, for gfx950.
+//
+// x pass, forward: a real row of N values is read as N/2 complex values
+// z[n] = x[2n] + i x[2n+1]; after a length-N/2 FFT, the spectrum of the row
+// is recovered for p in [0, N/2] from Z[p] and Z[N/2-p]:
+//   E = (Z[p] + conj Z[N/2-p]) / 2,  O = (Z[p] - conj Z[N/2-p]) / (2i),
+//   X[p] = E + W^p O,  X[N/2-p] = conj(E - W^p O),   W = exp(-2 pi i / N).
+// x pass, inverse: the same relation run backwards (unnormalised), giving
+// N x[2n] + i N x[2n+1] after a length-N/2 inverse FFT.
+#include "lc_fft_device.h"
+#include "lc_internal.h"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------
+// forward x pass
+// ---------------------------------------------------------------------------
+template <typename T, typename TIN, int N, bool DC>
+__global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
+    const TIN *__restrict__ in, cx<T> *__restrict__ mainp, cx<T> *__restrict__ nyq, int64_t n_rows,
+    const cx<T> *__restrict__ tw, const cx<T> *__restrict__ twist, double *__restrict__ dcpart) {
+    constexpr int L = N / 2;
+    using SH = RowShape<T, L>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD;
+    __shared__ cx<T> lds[RPW * LS];
+    __shared__ double red[NT / 64];
+
+    const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    double dsum = 0.0;
+    // coalesced load of RPW consecutive rows (one contiguous block)
+    for (int e = threadIdx.x; e < RPW * L; e += NT) {
+        const int rr = e / L, nn = e % L;
+        if (row0 + rr < n_rows) {
+            const int64_t g = (row0 + rr) * N + 2 * nn;
+            const TIN a = in[g], b = in[g + 1];
+            lds[rr * LS + nn] = mk((T)a, (T)b);
+            if (DC) dsum += (double)a + (double)b;
+        }
+    }
+    __syncthreads();
+    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    const bool active = (row0 + line) < n_rows;
+    fft_lds<T, L, true>(lds, line * LS, 1, t, active, tw);
+
+    if (active) {
+        const int64_t row = row0 + line;
+        const cx<T> *z = lds + line * LS;
+        for (int p = t; p <= L / 2; p += TPL) {
+            const cx<T> A = z[p], B = z[(L - p) % L];
+            const cx<T> E = mk((A.x + B.x) * (T)0.5, (A.y - B.y) * (T)0.5);
+            // O = (A - conj B) / (2i) = ((A.y + B.y), -(A.x - B.x)) / 2
+            const cx<T> O = mk((A.y + B.y) * (T)0.5, (B.x - A.x) * (T)0.5);
+            const cx<T> WO = cmul(twist[p], O);
+            const cx<T> Xp = E + WO;
+            const cx<T> Xm = conj(E - WO);
+            mainp[row * L + p] = Xp;
+            if (p == 0) nyq[row] = Xm;
+            else if (p != L - p) mainp[row * L + (L - p)] = Xm;
+        }
+    }
+    if (DC) {
+        // workgroup sum of the FP64 partials (fixed order: deterministic)
+        for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            dcpart[blockIdx.x] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inverse x pass + epilogue
+// ---------------------------------------------------------------------------
+template <typename T, typename TOUT, int N>
+__global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_inv_kernel(
+    const cx<T> *__restrict__ mainp, const cx<T> *__restrict__ nyq, TOUT *__restrict__ out,
+    int64_t n_rows, const cx<T> *__restrict__ tw, const cx<T> *__restrict__ twist, double scale,
+    const double *__restrict__ mu) {
+    constexpr int L = N / 2;
+    using SH = RowShape<T, L>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD;
+    __shared__ cx<T> lds[RPW * LS];
+
+    const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    const bool active = (row0 + line) < n_rows;
+    if (active) {
+        const int64_t row = row0 + line;
+        cx<T> *z = lds + line * LS;
+        for (int p = t; p <= L / 2; p += TPL) {
+            if (p == 0) {
+                const T x0 = mainp[row * L].x, xl = nyq[row].x;
+                z[0] = mk(x0 + xl, x0 - xl);
+            } else {
+                const cx<T> Xp = mainp[row * L + p], Xm = mainp[row * L + (L - p)];
+                const cx<T> Ep = Xp + conj(Xm);
+                const cx<T> D = Xp - conj(Xm);
+                const cx<T> Op = cmul(D, conj(twist[p]));
+                // Z[p] = Ep + i Op ; Z[L-p] = conj(Ep) + i conj(Op)
+                z[p] = mk(Ep.x - Op.y, Ep.y + Op.x);
+                if (p != L - p) z[L - p] = mk(Ep.x + Op.y, Op.x - Ep.y);
+            }
+        }
+    }
+    __syncthreads();
+    fft_lds<T, L, false>(lds, line * LS, 1, t, active, tw);
+    const double m = mu ? *mu : 0.0;
+    for (int e = threadIdx.x; e < RPW * L; e += NT) {
+        const int rr = e / L, nn = e % L;
+        if (row0 + rr < n_rows) {
+            const cx<T> v = lds[rr * LS + nn];
+            const int64_t g = (row0 + rr) * N + 2 * nn;
+            out[g] = (TOUT)((double)v.x * scale + m);
+            out[g + 1] = (TOUT)((double)v.y * scale + m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// column passes (y or z), in place; grid = main WGs then nyq WGs
+// ---------------------------------------------------------------------------
+template <typename T, int L, bool FWD>
+__global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(cx<T> *data, ColSet s0, ColSet s1,
+                                                                const cx<T> *__restrict__ tw) {
+    using SH = ColShape<T, L>;
+    constexpr int CPW = SH::CPW, NT = SH::NT, PAD = SH::PAD, ES = CPW + PAD;
+    __shared__ cx<T> lds[L * ES];
+    const bool first = (int)blockIdx.x < s0.n_wgs;
+    const ColSet &s = first ? s0 : s1;
+    const int64_t col0 = (int64_t)(first ? blockIdx.x : blockIdx.x - s0.n_wgs) * CPW;
+    tile_load<T, L, CPW, NT, PAD>(lds, data, s, col0);
+    __syncthreads();
+    const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
+    fft_lds<T, L, FWD>(lds, c, ES, t, true, tw);
+    tile_store<T, L, CPW, NT, PAD>(data, lds, s, col0);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+bool supported_n(int n) {
+    switch (n) {
+        case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
+        case 128: case 192: case 256: case 384: case 512: return true;
+        default: return false;
+    }
+}
+
+#define LC_DISPATCH_N(n, MACRO)                                                  \
+    switch (n) {                                                                 \
+        case 8: MACRO(8); break;     case 12: MACRO(12); break;                  \
+        case 16: MACRO(16); break;   case 24: MACRO(24); break;                  \
+        case 32: MACRO(32); break;   case 48: MACRO(48); break;                  \
+        case 64: MACRO(64); break;   case 96: MACRO(96); break;                  \
+        case 128: MACRO(128); break; case 192: MACRO(192); break;                \
+        case 256: MACRO(256); break; case 384: MACRO(384); break;                \
+        case 512: MACRO(512); break;                                             \
+        default: return hipErrorInvalidValue;                                    \
+    }
+
+template <int N> static int x_wgs_t() {
+    using SH = RowShape<float, N / 2>;
+    return (int)(((int64_t)N * N + SH::RPW - 1) / SH::RPW);
+}
+
+int x_pass_wgs(int n) {
+    switch (n) {
+#define W_(N) case N: return x_wgs_t<N>();
+        W_(8) W_(12) W_(16) W_(24) W_(32) W_(48) W_(64) W_(96) W_(128) W_(192) W_(256) W_(384) W_(512)
+#undef W_
+        default: return 0;
+    }
+}
+
+template <typename T, typename TIN, int N>
+static hipError_t x_fwd_t(const void *in, void *spec, const void *tw, const void *twist,
+                          double *dcpart, hipStream_t st) {
+    using SH = RowShape<T, N / 2>;
+    static_assert(SH::RPW == RowShape<float, N / 2>::RPW, "rows per WG must not depend on T");
+    const int64_t rows = (int64_t)N * N;
+    const int wgs = (int)((rows + SH::RPW - 1) / SH::RPW);
+    cx<T> *sp = (cx<T> *)spec;
+    if (dcpart)
+        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, true>), dim3(wgs), dim3(SH::NT), 0, st,
+                           (const TIN *)in, sp, sp + spec_main(N), rows, (const cx<T> *)tw,
+                           (const cx<T> *)twist, dcpart);
+    else
+        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, false>), dim3(wgs), dim3(SH::NT), 0, st,
+                           (const TIN *)in, sp, sp + spec_main(N), rows, (const cx<T> *)tw,
+                           (const cx<T> *)twist, dcpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_x_fwd(int n, bool t_f64, const void *in, bool in_f64, void *spec,
+                        const void *tw_half, const void *twist, double *dcpart, hipStream_t st) {
+#define X_(N)                                                                                \
+    if (t_f64) return in_f64 ? x_fwd_t<double, double, N>(in, spec, tw_half, twist, dcpart, st) \
+                             : x_fwd_t<double, float, N>(in, spec, tw_half, twist, dcpart, st); \
+    else return in_f64 ? x_fwd_t<float, double, N>(in, spec, tw_half, twist, dcpart, st)       \
+                       : x_fwd_t<float, float, N>(in, spec, tw_half, twist, dcpart, st);
+    LC_DISPATCH_N(n, X_)
+#undef X_
+    return hipErrorInvalidValue;
+}
+
+template <typename T, typename TOUT, int N>
+static hipError_t x_inv_t(const void *spec, void *out, const void *tw, const void *twist,
+                          double scale, const double *mu, hipStream_t st) {
+    using SH = RowShape<T, N / 2>;
+    const int64_t rows = (int64_t)N * N;
+    const int wgs = (int)((rows + SH::RPW - 1) / SH::RPW);
+    const cx<T> *sp = (const cx<T> *)spec;
+    hipLaunchKernelGGL((x_inv_kernel<T, TOUT, N>), dim3(wgs), dim3(SH::NT), 0, st, sp,
+                       sp + spec_main(N), (TOUT *)out, rows, (const cx<T> *)tw,
+                       (const cx<T> *)twist, scale, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_x_inv(int n, bool t_f64, const void *spec, void *out, bool out_f64,
+                        const void *tw_half, const void *twist, double scale, const double *mu,
+                        hipStream_t st) {
+#define X_(N)                                                                                     \
+    if (t_f64) return out_f64 ? x_inv_t<double, double, N>(spec, out, tw_half, twist, scale, mu, st) \
+                              : x_inv_t<double, float, N>(spec, out, tw_half, twist, scale, mu, st); \
+    else return out_f64 ? x_inv_t<float, double, N>(spec, out, tw_half, twist, scale, mu, st)       \
+                        : x_inv_t<float, float, N>(spec, out, tw_half, twist, scale, mu, st);
+    LC_DISPATCH_N(n, X_)
+#undef X_
+    return hipErrorInvalidValue;
+}
+
+// Column sets of the spectrum for a pass along axis 1 (y) or 2 (z).
+template <typename T, int N>
+static void col_sets(int axis, ColSet &s0, ColSet &s1) {
+    using SH = ColShape<T, N>;
+    const int64_t H = N / 2;
+    const int64_t main_n = spec_main(N);
+    if (axis == 1) {
+        // main: columns (z, p); element (row y) at z*N*H + y*H + p
+        s0.n_cols = (int64_t)N * H; s0.W = H; s0.plane_stride = (int64_t)N * H; s0.col_stride = 1;
+        s0.row_stride = H; s0.off = 0; s0.rowfast = 0;
+        // nyq: columns z; element (row y) at main_n + z*N + y
+        s1.n_cols = N; s1.W = N; s1.plane_stride = 0; s1.col_stride = N; s1.row_stride = 1;
+        s1.off = main_n; s1.rowfast = 1;
+    } else {
+        // main: columns (y, p) = flat y*H + p; element (row z) at z*N*H + col
+        s0.n_cols = (int64_t)N * H; s0.W = (int64_t)N * H; s0.plane_stride = 0; s0.col_stride = 1;
+        s0.row_stride = (int64_t)N * H; s0.off = 0; s0.rowfast = 0;
+        // nyq: columns y; element (row z) at main_n + z*N + y
+        s1.n_cols = N; s1.W = N; s1.plane_stride = 0; s1.col_stride = 1; s1.row_stride = N;
+        s1.off = main_n; s1.rowfast = 0;
+    }
+    s0.n_wgs = (int32_t)((s0.n_cols + SH::CPW - 1) / SH::CPW);
+    s1.n_wgs = (int32_t)((s1.n_cols + SH::CPW - 1) / SH::CPW);
+}
+
+template <typename T, int N>
+static hipError_t col_t(int axis, bool fwd, void *spec, const void *tw, hipStream_t st) {
+    using SH = ColShape<T, N>;
+    ColSet s0, s1;
+    col_sets<T, N>(axis, s0, s1);
+    const int wgs = s0.n_wgs + s1.n_wgs;
+    if (fwd)
+        hipLaunchKernelGGL((col_kernel<T, N, true>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec, s0,
+                           s1, (const cx<T> *)tw);
+    else
+        hipLaunchKernelGGL((col_kernel<T, N, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec, s0,
+                           s1, (const cx<T> *)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,
+                      hipStream_t st) {
+#define X_(N)                                                   \
+    if (t_f64) return col_t<double, N>(axis, fwd, spec, tw_full, st); \
+    else return col_t<float, N>(axis, fwd, spec, tw_full, st);
+    LC_DISPATCH_N(n, X_)
+#undef X_
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lc

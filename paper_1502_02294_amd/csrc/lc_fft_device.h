@@ -1,0 +1,331 @@
+// Device-side building blocks for the LDS-staged Stockham FFT passes on
+// gfx950 (wave64). Shared by every pass kernel of the library.
+//
+// A transform of length L is done by TPL threads per line; each pass of
+// radix R performs L/R butterflies. Inputs of butterfly b are read at
+// b + r*(L/R); outputs are written at (b/Ns)*Ns*R + b%Ns + r*Ns, where Ns
+// is the product of the radices of the earlier passes (mixed-radix
+// Stockham autosort, natural order in and out). Twiddles come from a table
+// W_L^j = exp(-2 pi i j/L) generated on the host in FP64; the inverse uses
+// their conjugates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cx<T> scal(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// multiply by the quarter-turn of the transform direction: -i forward, +i inverse
+template <bool FWD, typename T> __device__ __forceinline__ cx<T> qturn(cx<T> a) {
+    return FWD ? mk(a.y, -a.x) : mk(-a.y, a.x);
+}
+
+// multiply by exp(-+ i pi/4): (1 -+ i)/sqrt2
+template <bool FWD, typename T> __device__ __forceinline__ cx<T> eighth1(cx<T> a) {
+    const T h = (T)0.70710678118654752440;
+    return FWD ? mk(h * (a.x + a.y), h * (a.y - a.x)) : mk(h * (a.x - a.y), h * (a.x + a.y));
+}
+// multiply by exp(-+ 3 i pi/4): (-1 -+ i)/sqrt2
+template <bool FWD, typename T> __device__ __forceinline__ cx<T> eighth3(cx<T> a) {
+    const T h = (T)0.70710678118654752440;
+    return FWD ? mk(h * (a.y - a.x), -h * (a.x + a.y)) : mk(-h * (a.x + a.y), h * (a.x - a.y));
+}
+// multiply by a constant unit complex (c, s) of the forward direction,
+// conjugated for the inverse
+template <bool FWD, typename T> __device__ __forceinline__ cx<T> rot(cx<T> a, T c, T s) {
+    return FWD ? mk(a.x * c - a.y * s, a.x * s + a.y * c) : mk(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// ---- small DFTs, in place, natural order ------------------------------------
+
+template <bool FWD, typename T> __device__ __forceinline__ void dft2(cx<T> *v) {
+    cx<T> a = v[0];
+    v[0] = a + v[1];
+    v[1] = a - v[1];
+}
+
+template <bool FWD, typename T> __device__ __forceinline__ void dft3(cx<T> *v) {
+    const T half = (T)0.5, s3 = (T)0.86602540378443864676;   // sin(2 pi/3)
+    cx<T> t1 = v[1] + v[2], t2 = v[1] - v[2];
+    cx<T> m = mk(v[0].x - half * t1.x, v[0].y - half * t1.y);
+    // forward: -i*s3*t2 ; inverse: +i*s3*t2
+    cx<T> j = FWD ? mk(s3 * t2.y, -s3 * t2.x) : mk(-s3 * t2.y, s3 * t2.x);
+    v[0] = v[0] + t1;
+    v[1] = m + j;
+    v[2] = m - j;
+}
+
+template <bool FWD, typename T> __device__ __forceinline__ void dft4(cx<T> *v) {
+    cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
+    cx<T> s13 = v[1] + v[3], d13 = qturn<FWD>(v[1] - v[3]);
+    v[0] = s02 + s13;
+    v[2] = s02 - s13;
+    v[1] = d02 + d13;
+    v[3] = d02 - d13;
+}
+
+// 8 = 2 (inner, stride 4) x 4 (outer): y[k + 2q] = DFT4_q( W8^{jk} (x_j +- x_{j+4}) )
+template <bool FWD, typename T> __device__ __forceinline__ void dft8(cx<T> *v) {
+    cx<T> a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = v[j] + v[j + 4];
+        b[j] = v[j] - v[j + 4];
+    }
+    b[1] = eighth1<FWD>(b[1]);
+    b[2] = qturn<FWD>(b[2]);
+    b[3] = eighth3<FWD>(b[3]);
+    dft4<FWD>(a);
+    dft4<FWD>(b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[2 * q] = a[q];
+        v[2 * q + 1] = b[q];
+    }
+}
+
+// 16 = 4 (inner, stride 4) x 4 (outer): y[k + 4q] = DFT4_q( W16^{jk} DFT4_m(x_{j+4m})_k )
+template <bool FWD, typename T> __device__ __forceinline__ void dft16(cx<T> *v) {
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;  // cos, sin(pi/8)
+    cx<T> c[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cx<T> t[4] = {v[j], v[j + 4], v[j + 8], v[j + 12]};
+        dft4<FWD>(t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[j][k] = t[k];
+    }
+    // twiddles W16^{jk}, forward W16 = exp(-i pi/8)
+    c[1][1] = rot<FWD>(c[1][1], c1, -s1);
+    c[1][2] = eighth1<FWD>(c[1][2]);
+    c[1][3] = rot<FWD>(c[1][3], s1, -c1);
+    c[2][1] = eighth1<FWD>(c[2][1]);
+    c[2][2] = qturn<FWD>(c[2][2]);
+    c[2][3] = eighth3<FWD>(c[2][3]);
+    c[3][1] = rot<FWD>(c[3][1], s1, -c1);
+    c[3][2] = eighth3<FWD>(c[3][2]);
+    c[3][3] = rot<FWD>(c[3][3], -c1, s1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cx<T> t[4] = {c[0][k], c[1][k], c[2][k], c[3][k]};
+        dft4<FWD>(t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[k + 4 * q] = t[q];
+    }
+}
+
+template <int R, bool FWD, typename T> __device__ __forceinline__ void dft(cx<T> *v) {
+    if constexpr (R == 2) dft2<FWD>(v);
+    else if constexpr (R == 3) dft3<FWD>(v);
+    else if constexpr (R == 4) dft4<FWD>(v);
+    else if constexpr (R == 8) dft8<FWD>(v);
+    else if constexpr (R == 16) dft16<FWD>(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ---- radix schedules ----------------------------------------------------------
+// Forward passes use R[0..NP-1]; the inverse runs them reversed, so the last
+// forward pass and the first inverse pass share the same element-to-thread
+// placement (used by the fused slice-sum pass).
+
+template <int L> struct Sched;
+#define LC_SCHED(L_, NP_, R0, R1, R2, TPL_)                                   \
+    template <> struct Sched<L_> {                                            \
+        static constexpr int NP = NP_;                                        \
+        static constexpr int TPL = TPL_;                                      \
+        static constexpr int r(int i) { return i == 0 ? R0 : i == 1 ? R1 : R2; } \
+    };
+LC_SCHED(4, 1, 4, 0, 0, 1)
+LC_SCHED(6, 2, 3, 2, 0, 1)
+LC_SCHED(8, 1, 8, 0, 0, 1)
+LC_SCHED(12, 2, 4, 3, 0, 1)
+LC_SCHED(16, 1, 16, 0, 0, 1)
+LC_SCHED(24, 2, 8, 3, 0, 2)
+LC_SCHED(32, 2, 8, 4, 0, 2)
+LC_SCHED(48, 2, 16, 3, 0, 4)
+LC_SCHED(64, 2, 16, 4, 0, 4)
+LC_SCHED(96, 3, 8, 4, 3, 8)
+LC_SCHED(128, 2, 16, 8, 0, 8)
+LC_SCHED(192, 3, 16, 4, 3, 16)
+LC_SCHED(256, 2, 16, 16, 0, 16)
+LC_SCHED(384, 3, 16, 8, 3, 32)
+LC_SCHED(512, 3, 16, 8, 4, 32)
+#undef LC_SCHED
+
+template <int L, bool FWD> __device__ __host__ constexpr int pass_radix(int p) {
+    return FWD ? Sched<L>::r(p) : Sched<L>::r(Sched<L>::NP - 1 - p);
+}
+
+// ---- one Stockham pass, split in a read half and a write half ---------------
+// Line elements live in LDS at lds[lbase + i*es]; thread t in [0, TPL).
+
+template <typename T, int L, int R, int NS, int TPL, bool FWD>
+struct Pass {
+    static constexpr int NB = L / R;
+    static constexpr int BPT = (NB + TPL - 1) / TPL;
+    static constexpr bool EVEN = (NB % TPL) == 0;
+
+    // read, twiddle and transform this thread's butterflies into v
+    __device__ __forceinline__ static void read(const cx<T> *lds, int lbase, int es, int t,
+                                                const cx<T> *__restrict__ tw, cx<T> (&v)[BPT][R]) {
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int b = t + i * TPL;
+            if (EVEN || b < NB) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i][r] = lds[lbase + (b + r * NB) * es];
+                if constexpr (NS > 1) {
+                    const int base = (b % NS) * (L / (NS * R));
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        cx<T> w = tw[base * r];
+                        if (!FWD) w.y = -w.y;
+                        v[i][r] = cmul(v[i][r], w);
+                    }
+                }
+                dft<R, FWD>(v[i]);
+            }
+        }
+    }
+    __device__ __forceinline__ static void write(cx<T> *lds, int lbase, int es, int t,
+                                                 const cx<T> (&v)[BPT][R]) {
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int b = t + i * TPL;
+            if (EVEN || b < NB) {
+                const int o = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[lbase + (o + r * NS) * es] = v[i][r];
+            }
+        }
+    }
+    // position (row along the line) of element v[i][r] after the write
+    __device__ __forceinline__ static int out_pos(int t, int i, int r) {
+        const int b = t + i * TPL;
+        return (b / NS) * NS * R + (b % NS) + r * NS;
+    }
+};
+
+template <int L, bool FWD> __device__ __host__ constexpr int ns_before(int p) {
+    int ns = 1;
+    for (int i = 0; i < p; ++i) ns *= pass_radix<L, FWD>(i);
+    return ns;
+}
+
+// Run passes [P, PEND) of the schedule from LDS to LDS. Every thread of the
+// workgroup must call this (it contains barriers).
+template <typename T, int L, bool FWD, int P, int PEND>
+__device__ __forceinline__ void run_passes(cx<T> *lds, int lbase, int es, int t, bool active,
+                                           const cx<T> *__restrict__ tw) {
+    if constexpr (P < PEND) {
+        constexpr int R = pass_radix<L, FWD>(P);
+        constexpr int NS = ns_before<L, FWD>(P);
+        using PS = Pass<T, L, R, NS, Sched<L>::TPL, FWD>;
+        cx<T> v[PS::BPT][R];
+        if (active) PS::read(lds, lbase, es, t, tw, v);
+        __syncthreads();
+        if (active) PS::write(lds, lbase, es, t, v);
+        __syncthreads();
+        run_passes<T, L, FWD, P + 1, PEND>(lds, lbase, es, t, active, tw);
+    }
+}
+
+template <typename T, int L, bool FWD>
+__device__ __forceinline__ void fft_lds(cx<T> *lds, int lbase, int es, int t, bool active,
+                                        const cx<T> *__restrict__ tw) {
+    run_passes<T, L, FWD, 0, Sched<L>::NP>(lds, lbase, es, t, active, tw);
+}
+
+// Column sets: a batch of strided lines. Column c of the set has its element
+// at row j at  off + (c / W) * plane_stride + (c % W) * col_stride + j * row_stride.
+struct ColSet {
+    int64_t n_cols;
+    int64_t W;
+    int64_t plane_stride;
+    int64_t col_stride;
+    int64_t row_stride;
+    int64_t off;
+    int32_t rowfast;   // 1: lanes walk along rows when loading (row_stride == 1)
+    int32_t n_wgs;     // workgroups covering this set
+};
+
+__device__ __forceinline__ int64_t col_base(const ColSet &s, int64_t c) {
+    return s.off + (c / s.W) * s.plane_stride + (c % s.W) * s.col_stride;
+}
+
+// Global <-> LDS tile moves for CPW columns starting at col0. LDS layout
+// [row][CPW + PAD].
+template <typename T, int L, int CPW, int NT, int PAD>
+__device__ __forceinline__ void tile_load(cx<T> *lds, const cx<T> *__restrict__ g, const ColSet &s,
+                                          int64_t col0) {
+    constexpr int ES = CPW + PAD;
+    if (!s.rowfast) {
+        static_assert(NT % CPW == 0, "NT must be a multiple of CPW");
+        const int c = threadIdx.x % CPW;
+        const int64_t col = col0 + c;
+        if (col < s.n_cols) {
+            const int64_t base = col_base(s, col);
+            for (int j = threadIdx.x / CPW; j < L; j += NT / CPW)
+                lds[j * ES + c] = g[base + j * s.row_stride];
+        }
+    } else {
+        for (int e = threadIdx.x; e < L * CPW; e += NT) {
+            const int j = e % L, c = e / L;
+            const int64_t col = col0 + c;
+            if (col < s.n_cols) lds[j * ES + c] = g[col_base(s, col) + j * s.row_stride];
+        }
+    }
+}
+
+template <typename T, int L, int CPW, int NT, int PAD>
+__device__ __forceinline__ void tile_store(cx<T> *__restrict__ g, const cx<T> *lds, const ColSet &s,
+                                           int64_t col0) {
+    constexpr int ES = CPW + PAD;
+    if (!s.rowfast) {
+        const int c = threadIdx.x % CPW;
+        const int64_t col = col0 + c;
+        if (col < s.n_cols) {
+            const int64_t base = col_base(s, col);
+            for (int j = threadIdx.x / CPW; j < L; j += NT / CPW)
+                g[base + j * s.row_stride] = lds[j * ES + c];
+        }
+    } else {
+        for (int e = threadIdx.x; e < L * CPW; e += NT) {
+            const int j = e % L, c = e / L;
+            const int64_t col = col0 + c;
+            if (col < s.n_cols) g[col_base(s, col) + j * s.row_stride] = lds[j * ES + c];
+        }
+    }
+}
+
+// Launch shape of the column passes for a line length L and element type.
+template <typename T, int L> struct ColShape {
+    static constexpr int TPL = Sched<L>::TPL;
+    static constexpr int NT = (sizeof(T) == 4 && L >= 384) ? 512 : 256;
+    static constexpr int CPW = NT / TPL;
+    static constexpr int PAD = (sizeof(T) == 4) ? 1 : 1;
+};
+
+// Launch shape of the row (x) passes for half-length L = N/2.
+template <typename T, int L> struct RowShape {
+    static constexpr int TPL = Sched<L>::TPL;
+    static constexpr int NT = 256;
+    static constexpr int RPW = NT / TPL;
+    static constexpr int PAD = (sizeof(T) == 4) ? 8 : 4;
+};
+
+}  // namespace lc

@@ -1,0 +1,204 @@
+// Periodic retarded-time shell kernel G_k (Eq. 10, algorithm step 2) and the
+// folding of its FP64 spectrum (step 3), plus small utility kernels.
+//
+// Builder: one thread per cell of the non-negative octant c in [0, N/2]^3.
+// For every periodic image u whose cell box can reach [r_k, r_{k+1}) it sums
+// the m^3 subpoints with exact integer squared distance n (units of the
+// half-subcell h = L/(2 m N)) inside [T_k, T_{k+1}), each weighing
+// pref * phi(rho) / (4 pi rho^2) / m^3, rho = sqrt(n) h. G is even in every
+// axis, so the octant value is written to all of its mirror cells.
+#include <algorithm>
+
+#include "lc_fft_device.h"
+#include "lc_internal.h"
+
+namespace lc {
+
+__device__ __forceinline__ double phi_eval(int kind, double r, double a, double s, double p,
+                                           double c, double cut) {
+    if (kind == 0) return 1.0;
+    const double v = a * exp(-pow(r / s, p)) - c;
+    if (kind == 1) return v > 0.0 ? v : 0.0;
+    return r <= cut ? v : 0.0;
+}
+
+__global__ __launch_bounds__(256) void greens_build_kernel(BuildArgs a) {
+    const int n = a.n, H = n / 2 + 1;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= (int64_t)H * H * H) return;
+    const int ci = (int)(cell / ((int64_t)H * H)), cj = (int)((cell / H) % H), ck = (int)(cell % H);
+    const int m = a.m, U = a.images;
+    const double l = a.l;
+    const double four_pi = 12.566370614359172954;
+    const double wm = a.pref / ((double)m * m * m);
+    const double margin = 1e-9 * (a.r_hi + l);
+    double acc = 0.0;
+    for (int u0 = -U; u0 <= U; ++u0) {
+        const int64_t x0 = ci + (int64_t)u0 * n;
+        const double lo0 = (x0 - 0.5) * l, hi0 = (x0 + 0.5) * l;
+        const double nr0 = lo0 > 0 ? lo0 : (hi0 < 0 ? -hi0 : 0.0), fr0 = fmax(fabs(lo0), fabs(hi0));
+        for (int u1 = -U; u1 <= U; ++u1) {
+            const int64_t x1 = cj + (int64_t)u1 * n;
+            const double lo1 = (x1 - 0.5) * l, hi1 = (x1 + 0.5) * l;
+            const double nr1 = lo1 > 0 ? lo1 : (hi1 < 0 ? -hi1 : 0.0), fr1 = fmax(fabs(lo1), fabs(hi1));
+            for (int u2 = -U; u2 <= U; ++u2) {
+                const int64_t x2 = ck + (int64_t)u2 * n;
+                const double lo2 = (x2 - 0.5) * l, hi2 = (x2 + 0.5) * l;
+                const double nr2 = lo2 > 0 ? lo2 : (hi2 < 0 ? -hi2 : 0.0), fr2 = fmax(fabs(lo2), fabs(hi2));
+                const double dmin = sqrt(nr0 * nr0 + nr1 * nr1 + nr2 * nr2);
+                const double dmax = sqrt(fr0 * fr0 + fr1 * fr1 + fr2 * fr2);
+                if (dmin > a.r_hi + margin || dmax < a.r_lo - margin) continue;
+                if (a.self_pair && x0 == 0 && x1 == 0 && x2 == 0) {
+                    acc += a.self_val;     // zero unless this is slice 0
+                    continue;
+                }
+                for (int a0 = 0; a0 < m; ++a0) {
+                    const int64_t q0 = 2 * m * x0 + (2 * a0 + 1 - m);
+                    for (int a1 = 0; a1 < m; ++a1) {
+                        const int64_t q1 = 2 * m * x1 + (2 * a1 + 1 - m);
+                        const int64_t s01 = q0 * q0 + q1 * q1;
+                        for (int a2 = 0; a2 < m; ++a2) {
+                            const int64_t q2 = 2 * m * x2 + (2 * a2 + 1 - m);
+                            const int64_t nn = s01 + q2 * q2;
+                            const double dn = (double)nn;
+                            if (dn >= a.t_lo && dn < a.t_hi) {
+                                const double rho = sqrt(dn) * a.h;
+                                acc += wm * phi_eval(a.kind, rho, a.a, a.s, a.p, a.c, a.cut) /
+                                       (four_pi * rho * rho);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // mirror into the full grid
+    const int is[2] = {ci, (n - ci) % n}, js[2] = {cj, (n - cj) % n}, ks[2] = {ck, (n - ck) % n};
+    for (int a0 = 0; a0 < 2; ++a0)
+        for (int a1 = 0; a1 < 2; ++a1)
+            for (int a2 = 0; a2 < 2; ++a2)
+                a.grid[((int64_t)is[a0] * n + js[a1]) * n + ks[a2]] = acc;
+}
+
+hipError_t launch_greens_build(const BuildArgs &a, hipStream_t st) {
+    const int64_t H = a.n / 2 + 1;
+    const int64_t cells = H * H * H;
+    hipLaunchKernelGGL(greens_build_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fold: FP64 spectrum -> real octant of the plan precision
+// ---------------------------------------------------------------------------
+template <typename TO>
+__global__ __launch_bounds__(256) void greens_fold_kernel(const cx<double> *__restrict__ spec, TO *__restrict__ oct,
+                                                          int n, int conserve, double target_over_l3,
+                                                          double *__restrict__ dc,
+                                                          unsigned long long *__restrict__ maxima) {
+    const int H = n / 2, HP = H + 1;
+    const int64_t total = (int64_t)HP * HP * HP;
+    const int64_t main_n = (int64_t)n * n * H;
+    const double g00 = spec[0].x;
+    const double f = conserve ? target_over_l3 / g00 : 1.0;
+    double mim = 0.0, mre = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ((int64_t)HP * HP)), q = (int)((e / HP) % HP), p = (int)(e % HP);
+        cx<double> v;
+        int64_t o;
+        if (p < H) {
+            v = spec[((int64_t)r * n + q) * H + p];
+            o = ((int64_t)r * HP + q) * H + p;
+        } else {
+            v = spec[main_n + (int64_t)r * n + q];
+            o = (int64_t)HP * HP * H + (int64_t)r * HP + q;
+        }
+        oct[o] = (TO)(v.x * f);
+        mim = fmax(mim, fabs(v.y));
+        mre = fmax(mre, fabs(v.x));
+        if (e == 0) *dc = v.x * f;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mim = fmax(mim, __shfl_down(mim, o, 64));
+        mre = fmax(mre, __shfl_down(mre, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        // non-negative doubles order like their bit patterns
+        atomicMax(&maxima[0], (unsigned long long)__double_as_longlong(mim));
+        atomicMax(&maxima[1], (unsigned long long)__double_as_longlong(mre));
+    }
+}
+
+hipError_t launch_greens_fold(int n, const void *spec64, void *oct, bool oct_f64, int conserve,
+                              double target_over_l3, double *dc, unsigned long long *maxima,
+                              hipStream_t st) {
+    const int64_t HP = n / 2 + 1;
+    const int64_t total = HP * HP * HP;
+    const int wgs = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    if (oct_f64)
+        hipLaunchKernelGGL(greens_fold_kernel<double>, dim3(wgs), dim3(256), 0, st,
+                           (const cx<double> *)spec64, (double *)oct, n, conserve, target_over_l3, dc,
+                           maxima);
+    else
+        hipLaunchKernelGGL(greens_fold_kernel<float>, dim3(wgs), dim3(256), 0, st,
+                           (const cx<double> *)spec64, (float *)oct, n, conserve, target_over_l3, dc,
+                           maxima);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fill_f64_kernel(double *__restrict__ p, int64_t count, double v) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(wgs), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st) {
+    if (bytes <= 0) return hipSuccess;
+    if (bytes % 4) return hipErrorInvalidValue;
+    const int64_t count = bytes / 4;
+    const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(wgs), dim3(256), 0, st, (uint32_t *)p, count);
+    return hipGetLastError();
+}
+
+template <typename TL>
+__global__ __launch_bounds__(256) void deposit_kernel(double *__restrict__ grid, int64_t n_pts,
+                                                      const int64_t *__restrict__ cell,
+                                                      const TL *__restrict__ lum, int64_t n_cells) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_pts;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = cell[e];
+        if (c >= 0 && c < n_cells) atomicAdd(&grid[c], (double)lum[e]);
+    }
+}
+
+hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
+                          bool lum_f64, int64_t n_cells, hipStream_t st) {
+    if (n_pts <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((n_pts + 255) / 256, 8192);
+    if (lum_f64)
+        hipLaunchKernelGGL(deposit_kernel<double>, dim3(wgs), dim3(256), 0, st, grid, n_pts, cell,
+                           (const double *)lum, n_cells);
+    else
+        hipLaunchKernelGGL(deposit_kernel<float>, dim3(wgs), dim3(256), 0, st, grid, n_pts, cell,
+                           (const float *)lum, n_cells);
+    return hipGetLastError();
+}
+
+}  // namespace lc

@@ -1,0 +1,778 @@
+// Host side of the C ABI (include/lc.h): descriptor validation, workspace
+// layout, FP64 host constants and the launch sequences of the four calls.
+//
+// Host constants computed here in FP64 (or wider):
+//  * slice thresholds T_k = (r_k/h)^2, h = L/(2 m N)   (exact shell membership)
+//  * twiddle tables exp(-2 pi i j/L) from long double sin/cos
+//  * the self-cell value: cube average of pref*phi/(4 pi r^2) over one cell,
+//    reduced by the six-pyramid split to a face integral of
+//    (l/2) Phi(R) / (4 pi R^3), Phi(R) = int_0^R phi; Phi of the attenuated
+//    forms via the lower incomplete gamma function
+//  * shell integrals int_{r_k}^{r_{k+1}} phi (for the conserve option)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/lc.h"
+#include "lc_internal.h"
+
+using namespace lc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err = "no error";
+    return LC_OK;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---- special functions (host, FP64) ---------------------------------------
+
+// lower incomplete gamma gamma(a, x) for a > 0, x >= 0
+double lower_gamma(double a, double x) {
+    if (x <= 0.0) return 0.0;
+    if (x < a + 1.0) {
+        // series: x^a e^-x sum_n x^n / (a (a+1) ... (a+n))
+        double term = 1.0 / a, sum = term;
+        for (int n = 1; n < 500; ++n) {
+            term *= x / (a + n);
+            sum += term;
+            if (std::fabs(term) < 1e-18 * std::fabs(sum)) break;
+        }
+        return sum * std::exp(a * std::log(x) - x);
+    }
+    // continued fraction for the upper function (modified Lentz)
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 500; ++i) {
+        const double an = -i * (i - a);
+        b += 2.0;
+        d = an * d + b;
+        if (std::fabs(d) < tiny) d = tiny;
+        c = b + an / c;
+        if (std::fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (std::fabs(del - 1.0) < 1e-17) break;
+    }
+    const double upper = std::exp(a * std::log(x) - x) * h;
+    return std::tgamma(a) - upper;
+}
+
+struct Atten {
+    int kind;
+    double a, s, p, c, cut, pref;
+};
+
+// end of the support of phi (first radius beyond which phi vanishes)
+double support_end(const Atten &at) {
+    if (at.kind == 0) return INFINITY;
+    if (at.kind == 2) return at.cut;
+    if (at.c <= 0.0) return INFINITY;
+    if (at.a <= at.c) return 0.0;
+    return at.s * std::pow(std::log(at.a / at.c), 1.0 / at.p);
+}
+
+// Phi(R) = int_0^R phi: for kinds 1-2, int_0^U a e^{-(r/s)^p} dr - c U with
+// U = min(R, support end); the first term is a (s/p) gamma(1/p, (U/s)^p).
+double Phi(const Atten &at, double R) {
+    if (R <= 0.0) return 0.0;
+    if (at.kind == 0) return R;
+    const double U = std::min(R, support_end(at));
+    if (U <= 0.0) return 0.0;
+    return at.a * (at.s / at.p) * lower_gamma(1.0 / at.p, std::pow(U / at.s, at.p)) - at.c * U;
+}
+
+// Gauss-Legendre rule on [0, 1] (Newton on the three-term recurrence)
+void gauss01(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        long double z = std::cos(pi * (i + 0.75L) / (n + 0.5L)), dp = 0;
+        for (int it = 0; it < 60; ++it) {
+            long double p1 = 1, p2 = 0;
+            for (int j = 1; j <= n; ++j) {
+                long double p3 = p2;
+                p2 = p1;
+                p1 = ((2 * j - 1) * z * p2 - (j - 1) * p3) / j;
+            }
+            dp = n * (z * p1 - p2) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs((double)dz) < 1e-19) break;
+        }
+        {
+            long double p1 = 1, p2 = 0;
+            for (int j = 1; j <= n; ++j) {
+                long double p3 = p2;
+                p2 = p1;
+                p1 = ((2 * j - 1) * z * p2 - (j - 1) * p3) / j;
+            }
+            dp = n * (z * p1 - p2) / (z * z - 1);
+        }
+        x[i] = (double)(0.5L * (1 - z));
+        w[i] = (double)(1.0L / ((1 - z * z) * dp * dp));   // 2/(..) on [-1,1], halved
+    }
+}
+
+// Cube average of pref * phi / (4 pi r^2) over a cell of side l.
+double self_cell(const Atten &at, double l) {
+    const double pi = 3.141592653589793238462643383279502884;
+    std::vector<double> x, w;
+    if (at.kind == 0) {
+        // (3 / (pi l^2)) J2, J2 = int_0^1 atan(1/sqrt(1+y^2)) / sqrt(1+y^2) dy
+        gauss01(40, x, w);
+        double j2 = 0.0;
+        for (int i = 0; i < 40; ++i) {
+            const double a = std::sqrt(1.0 + x[i] * x[i]);
+            j2 += w[i] * std::atan(1.0 / a) / a;
+        }
+        return at.pref * 3.0 * j2 / (pi * l * l);
+    }
+    // (3 / (2 pi l^3)) * 4 * int_0^{l/2} int_0^{l/2} (l/2) Phi(R) / R^3, on 2 x 2 panels
+    gauss01(24, x, w);
+    const double hl = 0.5 * l, hp = 0.5 * hl;
+    double acc = 0.0;
+    for (int py = 0; py < 2; ++py)
+        for (int pz = 0; pz < 2; ++pz)
+            for (int i = 0; i < 24; ++i) {
+                const double y = hp * (py + x[i]);
+                for (int j = 0; j < 24; ++j) {
+                    const double z = hp * (pz + x[j]);
+                    const double R = std::sqrt(hl * hl + y * y + z * z);
+                    acc += w[i] * w[j] * hl * Phi(at, R) / (R * R * R);
+                }
+            }
+    acc *= hp * hp;
+    return at.pref * 3.0 * 4.0 * acc / (2.0 * pi * l * l * l);
+}
+
+// ---- twiddle tables -----------------------------------------------------------
+
+// exp(-2 pi i j / L) for j in [0, count), as (re, im) doubles
+void twiddles64(int L, int count, double *out) {
+    const long double pi2 = 6.283185307179586476925286766559005768L;
+    for (int j = 0; j < count; ++j) {
+        const long double ang = pi2 * (long double)j / (long double)L;
+        out[2 * j] = (double)cosl(ang);
+        out[2 * j + 1] = (double)(-sinl(ang));
+    }
+}
+
+// same in FP32 arithmetic throughout (the plain FP32 form)
+void twiddles32_plain(int L, int count, float *out) {
+    const float pi2 = 6.28318530717958647692f;
+    for (int j = 0; j < count; ++j) {
+        const float ang = pi2 * (float)j / (float)L;
+        out[2 * j] = cosf(ang);
+        out[2 * j + 1] = -sinf(ang);
+    }
+}
+
+bool is_2a3b(int n) {
+    if (n <= 0) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+}  // namespace
+
+// ---- plan --------------------------------------------------------------------
+
+struct BoxPlan {
+    int n = 0, K = 0, B = 0, m = 1, conserve = 0;
+    double L = 0, l = 0, h = 0;
+    std::vector<double> radii, T;
+    std::vector<int> built, kcount;
+    std::vector<uint8_t> pushed;
+    // device regions
+    char *spec = nullptr, *acc = nullptr, *ghat = nullptr;
+    double *ghat0 = nullptr, *dcpart = nullptr, *mu = nullptr;
+    unsigned long long *maxima = nullptr;
+    char *tw_half = nullptr, *tw_full = nullptr, *twist = nullptr;       // plan precision
+    char *tw64_half = nullptr, *tw64_full = nullptr, *twist64 = nullptr; // FP64 (builder)
+    int xwgs = 0;
+};
+
+struct lc_plan_s {
+    int prec = LC_PREC_FP64;
+    bool t_f64 = true;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int use_graph = 0;
+    std::vector<BoxPlan> boxes;
+    char *scratch_real = nullptr;    // FP64 N^3: builder grid / source staging / host-output staging
+    char *scratch_spec = nullptr;    // FP64 spectrum for the builder
+    // graph cache for lc_step
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<uint8_t> gkey;
+};
+
+namespace {
+
+struct Layout {
+    size_t total = 0;
+    struct BoxOff {
+        size_t spec, acc, ghat, ghat0, dcpart, mu, maxima, tw_half, tw_full, twist, tw64_half,
+            tw64_full, twist64;
+    };
+    std::vector<BoxOff> box;
+    size_t scratch_real = 0, scratch_spec = 0;
+};
+
+int validate(const lc_plan_desc *d) {
+    if (!d) return fail(LC_EINVAL, "descriptor is NULL");
+    if (d->reserved != 0) return fail(LC_EINVAL, "reserved field must be 0");
+    if (d->n_boxes < 1 || d->n_boxes > 4096) return fail(LC_EINVAL, "n_boxes must be in [1, 4096]");
+    if (!d->boxes) return fail(LC_EINVAL, "boxes is NULL");
+    if (d->precision != LC_PREC_FP64 && d->precision != LC_PREC_FP32_PLAIN && d->precision != LC_PREC_FP32)
+        return fail(LC_EINVAL, "unknown precision %d", d->precision);
+    if (d->use_graph != 0 && d->use_graph != 1) return fail(LC_EINVAL, "use_graph must be 0 or 1");
+    for (int b = 0; b < d->n_boxes; ++b) {
+        const lc_box_desc &x = d->boxes[b];
+        if (x.reserved != 0) return fail(LC_EINVAL, "box %d: reserved field must be 0", b);
+        if (x.n < 8 || x.n > 1024 || (x.n % 2) || !is_2a3b(x.n))
+            return fail(LC_EUNSUPPORTED, "box %d: N=%d must be even, 2^a 3^b, in 8..1024", b, x.n);
+        if (!supported_n(x.n))
+            return fail(LC_EUNSUPPORTED, "box %d: N=%d is not compiled in (8..512)", b, x.n);
+        if (x.n_slices < 1 || x.n_slices > 1024)
+            return fail(LC_EINVAL, "box %d: n_slices must be in [1, 1024]", b);
+        if (x.n_bands < 1 || x.n_bands > 64) return fail(LC_EINVAL, "box %d: n_bands must be in [1, 64]", b);
+        if (x.supersample < 1 || x.supersample > 8)
+            return fail(LC_EUNSUPPORTED, "box %d: supersample must be in [1, 8]", b);
+        if (x.conserve != 0 && x.conserve != 1) return fail(LC_EINVAL, "box %d: conserve must be 0 or 1", b);
+        if (!(x.box > 0.0) || !std::isfinite(x.box)) return fail(LC_EINVAL, "box %d: box length must be > 0", b);
+        if (!x.radii) return fail(LC_EINVAL, "box %d: radii is NULL", b);
+        for (int k = 0; k <= x.n_slices; ++k)
+            if (!std::isfinite(x.radii[k])) return fail(LC_EINVAL, "box %d: radius %d not finite", b, k);
+        if (x.radii[0] < 0.0) return fail(LC_EINVAL, "box %d: r_0 must be >= 0", b);
+        for (int k = 0; k < x.n_slices; ++k)
+            if (!(x.radii[k + 1] > x.radii[k]))
+                return fail(LC_EINVAL, "box %d: radii must be strictly increasing", b);
+        const double l = x.box / x.n;
+        if (x.radii[0] == 0.0 && x.radii[1] < 0.5 * std::sqrt(3.0) * l)
+            return fail(LC_EUNSUPPORTED,
+                        "box %d: r_1 = %g < (sqrt 3 / 2) l = %g: the self cell would straddle slices", b,
+                        x.radii[1], 0.5 * std::sqrt(3.0) * l);
+        // image range and exact-integer headroom
+        const double U = std::ceil(x.radii[x.n_slices] / x.box) + 1.0;
+        const double qmax = 2.0 * x.supersample * (U + 1.0) * x.n + x.supersample;
+        if (3.0 * qmax * qmax > 9.0e15)
+            return fail(LC_EUNSUPPORTED, "box %d: outer radius too large for exact distances", b);
+        if (U > 64) return fail(LC_EUNSUPPORTED, "box %d: outer radius spans more than 63 box lengths", b);
+    }
+    return LC_OK;
+}
+
+Layout layout_of(const lc_plan_desc *d) {
+    Layout lay;
+    const bool f64 = d->precision == LC_PREC_FP64;
+    const size_t cs = f64 ? 16 : 8, rs = f64 ? 8 : 4;
+    size_t off = 0, max_real = 0, max_spec = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    for (int b = 0; b < d->n_boxes; ++b) {
+        const lc_box_desc &x = d->boxes[b];
+        const int n = x.n, K = x.n_slices, B = x.n_bands;
+        Layout::BoxOff o;
+        o.spec = take((size_t)K * spec_elems(n) * cs);
+        o.acc = take((size_t)B * spec_elems(n) * cs);
+        o.ghat = take((size_t)K * B * oct_elems(n) * rs);
+        o.ghat0 = take((size_t)K * B * 8);
+        o.dcpart = take((size_t)K * x_pass_wgs(n) * 8);
+        o.mu = take((size_t)B * 8);
+        o.maxima = take((size_t)B * 2 * 8);
+        o.tw_half = take((size_t)(n / 2) * cs);
+        o.tw_full = take((size_t)n * cs);
+        o.twist = take((size_t)(n / 2) * cs);
+        o.tw64_half = take((size_t)(n / 2) * 16);
+        o.tw64_full = take((size_t)n * 16);
+        o.twist64 = take((size_t)(n / 2) * 16);
+        lay.box.push_back(o);
+        max_real = std::max(max_real, (size_t)n * n * n * 8);
+        max_spec = std::max(max_spec, (size_t)spec_elems(n) * 16);
+    }
+    lay.scratch_real = take(max_real);
+    lay.scratch_spec = take(max_spec);
+    lay.total = off;
+    return lay;
+}
+
+int check_device() {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(LC_EDEVICE, "no HIP device available");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LC_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(LC_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(LC_EDEVICE, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    return LC_OK;
+}
+
+int upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return LC_OK;
+}
+
+Atten atten_of(const lc_atten *a) {
+    Atten r;
+    r.kind = a->kind; r.a = a->a; r.s = a->s; r.p = a->p; r.c = a->c; r.cut = a->cut;
+    r.pref = a->prefactor;
+    return r;
+}
+
+int valid_sources(const BoxPlan &bp, const lc_sources *s) {
+    if (!s) return fail(LC_EINVAL, "sources is NULL");
+    if (s->reserved != 0) return fail(LC_EINVAL, "sources.reserved must be 0");
+    if (s->dtype != LC_F32 && s->dtype != LC_F64) return fail(LC_EINVAL, "bad source dtype");
+    if (s->mem != LC_MEM_HOST && s->mem != LC_MEM_DEVICE) return fail(LC_EINVAL, "bad source mem");
+    if (s->kind == 0) {
+        if (!s->grid) return fail(LC_EINVAL, "dense source grid is NULL");
+    } else if (s->kind == 1) {
+        if (s->n < 0) return fail(LC_EINVAL, "point count must be >= 0");
+        if (s->n > 0 && (!s->cell || !s->lum)) return fail(LC_EINVAL, "point list pointers are NULL");
+        if (s->mem == LC_MEM_HOST) {
+            const int64_t n3 = (int64_t)bp.n * bp.n * bp.n;
+            for (int64_t i = 0; i < s->n; ++i)
+                if (s->cell[i] < 0 || s->cell[i] >= n3)
+                    return fail(LC_EINVAL, "point %lld: cell %lld outside [0, N^3)", (long long)i,
+                                (long long)s->cell[i]);
+        }
+    } else {
+        return fail(LC_EINVAL, "unknown source kind %d", s->kind);
+    }
+    return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lc_workspace_bytes(const lc_plan_desc *desc) {
+    if (validate(desc) != LC_OK) return 0;
+    ok();
+    return layout_of(desc).total;
+}
+
+int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
+    if (!out) return fail(LC_EINVAL, "out is NULL");
+    int rc = validate(d);
+    if (rc) return rc;
+    const Layout lay = layout_of(d);
+    if (!d->workspace) return fail(LC_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d->workspace) % kAlign) return fail(LC_ENOMEM, "workspace must be 256-byte aligned");
+    if (d->workspace_bytes < lay.total)
+        return fail(LC_ENOMEM, "workspace of %zu bytes < %zu required", d->workspace_bytes, lay.total);
+    if ((rc = check_device())) return rc;
+
+    std::unique_ptr<lc_plan_s> p(new lc_plan_s());
+    p->prec = d->precision;
+    p->t_f64 = d->precision == LC_PREC_FP64;
+    p->stream = (hipStream_t)d->hip_stream;
+    p->ws = (char *)d->workspace;
+    p->ws_bytes = d->workspace_bytes;
+    p->use_graph = d->use_graph;
+    p->scratch_real = p->ws + lay.scratch_real;
+    p->scratch_spec = p->ws + lay.scratch_spec;
+    const size_t cs = p->t_f64 ? 16 : 8;
+    for (int b = 0; b < d->n_boxes; ++b) {
+        const lc_box_desc &x = d->boxes[b];
+        const Layout::BoxOff &o = lay.box[b];
+        BoxPlan bp;
+        bp.n = x.n; bp.K = x.n_slices; bp.B = x.n_bands; bp.m = x.supersample; bp.conserve = x.conserve;
+        bp.L = x.box;
+        bp.l = x.box / x.n;
+        bp.h = x.box / (2.0 * x.supersample * x.n);
+        bp.radii.assign(x.radii, x.radii + x.n_slices + 1);
+        bp.T.resize(bp.K + 1);
+        for (int k = 0; k <= bp.K; ++k) {
+            const double q = bp.radii[k] / bp.h;
+            bp.T[k] = q * q;
+        }
+        bp.built.assign(bp.B, 0);
+        bp.kcount.assign(bp.B, bp.K);
+        bp.pushed.assign(bp.K, 0);
+        bp.spec = p->ws + o.spec; bp.acc = p->ws + o.acc; bp.ghat = p->ws + o.ghat;
+        bp.ghat0 = (double *)(p->ws + o.ghat0); bp.dcpart = (double *)(p->ws + o.dcpart);
+        bp.mu = (double *)(p->ws + o.mu); bp.maxima = (unsigned long long *)(p->ws + o.maxima);
+        bp.tw_half = p->ws + o.tw_half; bp.tw_full = p->ws + o.tw_full; bp.twist = p->ws + o.twist;
+        bp.tw64_half = p->ws + o.tw64_half; bp.tw64_full = p->ws + o.tw64_full;
+        bp.twist64 = p->ws + o.twist64;
+        bp.xwgs = x_pass_wgs(bp.n);
+
+        // tables
+        const int n = bp.n;
+        std::vector<double> th(n), tf(2 * n), tt(n);
+        twiddles64(n / 2, n / 2, th.data());
+        twiddles64(n, n, tf.data());
+        twiddles64(n, n / 2, tt.data());
+        if ((rc = upload(bp.tw64_half, th.data(), (size_t)n / 2 * 16, p->stream))) return rc;
+        if ((rc = upload(bp.tw64_full, tf.data(), (size_t)n * 16, p->stream))) return rc;
+        if ((rc = upload(bp.twist64, tt.data(), (size_t)n / 2 * 16, p->stream))) return rc;
+        if (p->t_f64) {
+            if ((rc = upload(bp.tw_half, th.data(), (size_t)n / 2 * 16, p->stream))) return rc;
+            if ((rc = upload(bp.tw_full, tf.data(), (size_t)n * 16, p->stream))) return rc;
+            if ((rc = upload(bp.twist, tt.data(), (size_t)n / 2 * 16, p->stream))) return rc;
+        } else {
+            std::vector<float> fh(n), ff(2 * n), ft(n);
+            if (p->prec == LC_PREC_FP32) {
+                for (int i = 0; i < n; ++i) fh[i] = (float)th[i];
+                for (int i = 0; i < 2 * n; ++i) ff[i] = (float)tf[i];
+                for (int i = 0; i < n; ++i) ft[i] = (float)tt[i];
+            } else {
+                twiddles32_plain(n / 2, n / 2, fh.data());
+                twiddles32_plain(n, n, ff.data());
+                twiddles32_plain(n, n / 2, ft.data());
+            }
+            if ((rc = upload(bp.tw_half, fh.data(), (size_t)n / 2 * 8, p->stream))) return rc;
+            if ((rc = upload(bp.tw_full, ff.data(), (size_t)n * 8, p->stream))) return rc;
+            if ((rc = upload(bp.twist, ft.data(), (size_t)n / 2 * 8, p->stream))) return rc;
+        }
+        // slices never pushed are zero
+        HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
+        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.xwgs, 0.0, p->stream));
+        HIPCHK(launch_fill_f64(bp.ghat0, (int64_t)bp.K * bp.B, 0.0, p->stream));
+        p->boxes.push_back(std::move(bp));
+    }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    *out = p.release();
+    return ok();
+}
+
+void lc_destroy(lc_plan_t *p) {
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+}
+
+const char *lc_last_error(void) { return g_err.c_str(); }
+
+int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range", band);
+    if (!at) return fail(LC_EINVAL, "atten is NULL");
+    if (at->reserved != 0) return fail(LC_EINVAL, "atten.reserved must be 0");
+    if (at->kind < 0 || at->kind > 2) return fail(LC_EINVAL, "unknown atten kind %d", at->kind);
+    if (!std::isfinite(at->prefactor)) return fail(LC_EINVAL, "prefactor must be finite");
+    if (at->kind != 0) {
+        if (!(at->a > 0) || !(at->s > 0) || !(at->p > 0) || !std::isfinite(at->c) || !std::isfinite(at->a) ||
+            !std::isfinite(at->s) || !std::isfinite(at->p))
+            return fail(LC_EINVAL, "atten needs finite a, s, p > 0 and finite c");
+        if (at->kind == 2 && !(at->cut >= 0 && std::isfinite(at->cut)))
+            return fail(LC_EINVAL, "atten kind 2 needs a finite cut >= 0");
+    }
+    const Atten A = atten_of(at);
+    const int n = bp.n, K = bp.K;
+    const double end = support_end(A);
+    int kc = 0;
+    while (kc < K && bp.radii[kc] < end) ++kc;
+    const double self = bp.radii[0] == 0.0 ? self_cell(A, bp.l) : 0.0;
+    const double l3 = bp.l * bp.l * bp.l;
+    const int U = (int)std::ceil(bp.radii[K] / bp.L) + 1;
+    const bool oct_f64 = p->t_f64;
+    const size_t rs = oct_f64 ? 8 : 4;
+    hipStream_t st = p->stream;
+
+    HIPCHK(launch_fill_bytes(bp.maxima + 2 * band, 16, st));
+    for (int k = 0; k < K; ++k) {
+        char *oct = bp.ghat + ((size_t)k * bp.B + band) * oct_elems(n) * rs;
+        double *dc = bp.ghat0 + (size_t)k * bp.B + band;
+        if (k >= kc) {
+            HIPCHK(launch_fill_bytes(oct, oct_elems(n) * rs, st));
+            HIPCHK(launch_fill_f64(dc, 1, 0.0, st));
+            continue;
+        }
+        BuildArgs a;
+        a.grid = (double *)p->scratch_real;
+        a.n = n; a.m = bp.m; a.l = bp.l; a.h = bp.h;
+        a.t_lo = bp.T[k]; a.t_hi = bp.T[k + 1];
+        a.r_lo = bp.radii[k]; a.r_hi = bp.radii[k + 1];
+        a.images = U;
+        a.self_pair = bp.radii[0] == 0.0 ? 1 : 0;
+        a.self_val = (k == 0) ? self : 0.0;
+        a.kind = A.kind; a.a = A.a; a.s = A.s; a.p = A.p; a.c = A.c; a.cut = A.cut; a.pref = A.pref;
+        HIPCHK(launch_greens_build(a, st));
+        HIPCHK(launch_x_fwd(n, true, p->scratch_real, true, p->scratch_spec, bp.tw64_half, bp.twist64,
+                            nullptr, st));
+        HIPCHK(launch_col(n, true, 1, true, p->scratch_spec, bp.tw64_full, st));
+        HIPCHK(launch_col(n, true, 2, true, p->scratch_spec, bp.tw64_full, st));
+        const double target = bp.conserve ? (Phi(A, bp.radii[k + 1]) - Phi(A, bp.radii[k])) / l3 : 0.0;
+        HIPCHK(launch_greens_fold(n, p->scratch_spec, oct, oct_f64, bp.conserve, target, dc,
+                                  bp.maxima + 2 * band, st));
+    }
+    bp.kcount[band] = kc;
+    bp.built[band] = 1;
+    return ok();
+}
+
+static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
+    BoxPlan &bp = p->boxes[box];
+    const int n = bp.n;
+    const int64_t n3 = (int64_t)n * n * n;
+    hipStream_t st = p->stream;
+    const void *in = nullptr;
+    bool in_f64 = s->dtype == LC_F64;
+    if (s->kind == 0) {
+        if (s->mem == LC_MEM_DEVICE) {
+            in = s->grid;
+        } else {
+            HIPCHK(hipMemcpyAsync(p->scratch_real, s->grid, (size_t)n3 * (in_f64 ? 8 : 4),
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            in = p->scratch_real;
+        }
+    } else {
+        in_f64 = true;
+        if (s->mem == LC_MEM_DEVICE) {
+            HIPCHK(launch_fill_f64((double *)p->scratch_real, n3, 0.0, st));
+            HIPCHK(launch_deposit((double *)p->scratch_real, s->n, s->cell, s->lum, s->dtype == LC_F64, n3, st));
+        } else {
+            std::vector<double> g((size_t)n3, 0.0);
+            for (int64_t i = 0; i < s->n; ++i)
+                g[(size_t)s->cell[i]] += s->dtype == LC_F64 ? ((const double *)s->lum)[i]
+                                                            : (double)((const float *)s->lum)[i];
+            HIPCHK(hipMemcpyAsync(p->scratch_real, g.data(), (size_t)n3 * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        in = p->scratch_real;
+    }
+    const size_t cs = p->t_f64 ? 16 : 8;
+    char *spec = bp.spec + (size_t)slice * spec_elems(n) * cs;
+    double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slice * bp.xwgs : nullptr;
+    HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, spec, bp.tw_half, bp.twist, dcp, st));
+    HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
+    if (p->prec != LC_PREC_FP32) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
+    bp.pushed[slice] = 1;
+    return LC_OK;
+}
+
+int lc_push_sources(lc_plan_t *p, int32_t box, int32_t slice, const lc_sources *s) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    if (slice < 0 || slice >= bp.K) return fail(LC_EINVAL, "slice %d out of range", slice);
+    int rc = valid_sources(bp, s);
+    if (rc) return rc;
+    rc = push_impl(p, box, slice, s);
+    return rc ? rc : ok();
+}
+
+// Field of one box for bands [b0, b1) into device pointers outp[b - b0].
+static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64) {
+    BoxPlan &bp = p->boxes[box];
+    const int n = bp.n, K = bp.K;
+    const size_t cs = p->t_f64 ? 16 : 8;
+    const int64_t se = spec_elems(n);
+    const double inv_n3 = 1.0 / ((double)n * n * n);
+    hipStream_t st = p->stream;
+    if (p->prec == LC_PREC_FP32) {
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.xwgs, bp.ghat0, bp.B, inv_n3, bp.mu, st));
+        for (int b = b0; b < b1;) {
+            const int nb = std::min(2, b1 - b);
+            FusedArgs fa;
+            fa.spec = bp.spec; fa.spec_stride = se;
+            fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
+            fa.K = K; fa.B = bp.B; fa.band0 = b; fa.nband = nb;
+            fa.kcount[0] = bp.kcount[b];
+            fa.kcount[1] = nb > 1 ? bp.kcount[b + 1] : 0;
+            fa.acc = bp.acc + (size_t)b * se * cs; fa.acc_stride = se;
+            fa.zero_dc = 1; fa.kahan = 1;
+            HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
+            b += nb;
+        }
+        for (int b = b0; b < b1; ++b) {
+            char *acc = bp.acc + (size_t)b * se * cs;
+            HIPCHK(launch_col(n, false, 1, false, acc, bp.tw_full, st));
+            HIPCHK(launch_x_inv(n, false, acc, outp[b - b0], out_f64, bp.tw_half, bp.twist, inv_n3, bp.mu + b,
+                                st));
+        }
+    } else {
+        for (int b = b0; b < b1; ++b) {
+            char *acc = bp.acc + (size_t)b * se * cs;
+            const size_t rs = p->t_f64 ? 8 : 4;
+            const int kc = bp.kcount[b];
+            if (kc == 0) HIPCHK(launch_fill_bytes(acc, se * cs, st));
+            for (int k = 0; k < kc; ++k)
+                HIPCHK(launch_mac_plain(n, p->t_f64, acc, bp.spec + (size_t)k * se * cs,
+                                        bp.ghat + ((size_t)k * bp.B + b) * oct_elems(n) * rs, k == 0, st));
+            HIPCHK(launch_col(n, p->t_f64, 2, false, acc, bp.tw_full, st));
+            HIPCHK(launch_col(n, p->t_f64, 1, false, acc, bp.tw_full, st));
+            HIPCHK(launch_x_inv(n, p->t_f64, acc, outp[b - b0], out_f64, bp.tw_half, bp.twist, inv_n3, nullptr,
+                                st));
+        }
+    }
+    return LC_OK;
+}
+
+int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t dtype, int32_t mem) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (!out) return fail(LC_EINVAL, "out is NULL");
+    if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad output dtype");
+    if (mem != LC_MEM_HOST && mem != LC_MEM_DEVICE) return fail(LC_EINVAL, "bad output mem");
+    const int nbx = (int)p->boxes.size();
+    if (box < -1 || box >= nbx) return fail(LC_EINVAL, "box %d out of range", box);
+    const int x0 = box < 0 ? 0 : box, x1 = box < 0 ? nbx : box + 1;
+    size_t nout = 0;
+    for (int x = x0; x < x1; ++x) {
+        const BoxPlan &bp = p->boxes[x];
+        if (band < -1 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range for box %d", band, x);
+        const int b0 = band < 0 ? 0 : band, b1 = band < 0 ? bp.B : band + 1;
+        for (int b = b0; b < b1; ++b) {
+            if (!bp.built[b]) return fail(LC_ESTATE, "kernel of box %d band %d not built", x, b);
+            if (!out[nout]) return fail(LC_EINVAL, "output pointer %zu is NULL", nout);
+            ++nout;
+        }
+    }
+    const bool f64 = dtype == LC_F64;
+    size_t o = 0;
+    for (int x = x0; x < x1; ++x) {
+        BoxPlan &bp = p->boxes[x];
+        const int b0 = band < 0 ? 0 : band, b1 = band < 0 ? bp.B : band + 1;
+        if (mem == LC_MEM_DEVICE) {
+            int rc = field_box(p, x, b0, b1, out + o, f64);
+            if (rc) return rc;
+        } else {
+            const size_t bytes = (size_t)bp.n * bp.n * bp.n * (f64 ? 8 : 4);
+            for (int b = b0; b < b1; ++b) {
+                void *dev = p->scratch_real;
+                int rc = field_box(p, x, b, b + 1, &dev, f64);
+                if (rc) return rc;
+                HIPCHK(hipMemcpyAsync(out[o + (b - b0)], dev, bytes, hipMemcpyDeviceToHost, p->stream));
+                HIPCHK(hipStreamSynchronize(p->stream));
+            }
+        }
+        o += (size_t)(b1 - b0);
+    }
+    return ok();
+}
+
+static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtype) {
+    size_t si = 0, oi = 0;
+    for (int x = 0; x < (int)p->boxes.size(); ++x) {
+        BoxPlan &bp = p->boxes[x];
+        for (int k = 0; k < bp.K; ++k) {
+            int rc = push_impl(p, x, k, &srcs[si++]);
+            if (rc) return rc;
+        }
+    }
+    for (int x = 0; x < (int)p->boxes.size(); ++x) {
+        BoxPlan &bp = p->boxes[x];
+        int rc = field_box(p, x, 0, bp.B, out + oi, dtype == LC_F64);
+        if (rc) return rc;
+        oi += bp.B;
+    }
+    return LC_OK;
+}
+
+int lc_step(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtype) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (!srcs || !out) return fail(LC_EINVAL, "srcs/out is NULL");
+    if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad output dtype");
+    size_t ns = 0, no = 0;
+    for (auto &bp : p->boxes) {
+        for (int b = 0; b < bp.B; ++b)
+            if (!bp.built[b]) return fail(LC_ESTATE, "a kernel is not built");
+        for (int k = 0; k < bp.K; ++k) {
+            const lc_sources *s = &srcs[ns++];
+            int rc = valid_sources(bp, s);
+            if (rc) return rc;
+            if (s->mem != LC_MEM_DEVICE) return fail(LC_EINVAL, "lc_step takes device sources only");
+        }
+        for (int b = 0; b < bp.B; ++b)
+            if (!out[no++]) return fail(LC_EINVAL, "output pointer is NULL");
+    }
+    if (!p->use_graph) {
+        int rc = step_impl(p, srcs, out, dtype);
+        return rc ? rc : ok();
+    }
+    // graph key: the argument bytes that determine the launch sequence
+    std::vector<uint8_t> key(sizeof(int32_t));
+    std::memcpy(key.data(), &dtype, sizeof(int32_t));
+    key.insert(key.end(), (const uint8_t *)srcs, (const uint8_t *)(srcs + ns));
+    key.insert(key.end(), (const uint8_t *)out, (const uint8_t *)(out + no));
+    if (!p->gexec || key != p->gkey) {
+        if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+        HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        int rc = step_impl(p, srcs, out, dtype);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->stream, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(LC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        p->graph = g;
+        HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        p->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(p->gexec, p->stream));
+    return ok();
+}
+
+int lc_greens_imag_ratio(lc_plan_t *p, int32_t box, int32_t band, double *ratio) {
+    if (!p || !ratio) return fail(LC_EINVAL, "NULL argument");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box out of range");
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band out of range");
+    if (!bp.built[band]) return fail(LC_ESTATE, "kernel not built");
+    unsigned long long m[2];
+    HIPCHK(hipMemcpyAsync(m, bp.maxima + 2 * band, 16, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    double mi, mr;
+    std::memcpy(&mi, &m[0], 8);
+    std::memcpy(&mr, &m[1], 8);
+    *ratio = mr > 0 ? mi / mr : 0.0;
+    return ok();
+}
+
+int lc_greens_dc(lc_plan_t *p, int32_t box, int32_t band, double *dc) {
+    if (!p || !dc) return fail(LC_EINVAL, "NULL argument");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box out of range");
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band out of range");
+    if (!bp.built[band]) return fail(LC_ESTATE, "kernel not built");
+    std::vector<double> all((size_t)bp.K * bp.B);
+    HIPCHK(hipMemcpyAsync(all.data(), bp.ghat0, all.size() * 8, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int k = 0; k < bp.K; ++k) dc[k] = all[(size_t)k * bp.B + band];
+    return ok();
+}
+
+}  // extern "C"

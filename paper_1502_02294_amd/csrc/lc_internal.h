@@ -1,0 +1,98 @@
+// Internal interface between the host plan code and the HIP kernel
+// launchers. Not installed; the public interface is include/lc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lc {
+
+// Spectrum of one real N^3 grid, x (contiguous) axis halved:
+//   main: [z][y][p],  p in [0, N/2)      N*N*(N/2) complex
+//   nyq : [z][y]      (p = N/2)          N*N complex
+inline int64_t spec_main(int n) { return (int64_t)n * n * (n / 2); }
+inline int64_t spec_elems(int n) { return spec_main(n) + (int64_t)n * n; }
+// Kernel spectrum octant (real, folded |r|, |q| in [0, N/2]):
+//   main: [r][q][p], p in [0, N/2)       H*H*(N/2) reals, H = N/2+1
+//   nyq : [r][q]                         H*H reals
+inline int64_t oct_main(int n) { int64_t h = n / 2 + 1; return h * h * (n / 2); }
+inline int64_t oct_elems(int n) { int64_t h = n / 2 + 1; return h * h * (n / 2 + 1); }
+
+bool supported_n(int n);
+
+// Number of workgroups of the forward x pass (rows per WG depends on N);
+// the DC partial array of one slice has this many doubles.
+int x_pass_wgs(int n);
+
+// Forward x pass: real rows -> main/nyq. in_f64 selects the input type,
+// t_f64 the working precision. dcpart (nullable) receives one FP64 partial
+// sum of the input per workgroup.
+hipError_t launch_x_fwd(int n, bool t_f64, const void *in, bool in_f64, void *spec,
+                        const void *tw_half, const void *twist, double *dcpart,
+                        hipStream_t st);
+
+// Inverse x pass + epilogue: out = scale * x + (mu ? *mu : 0), cast to out type.
+hipError_t launch_x_inv(int n, bool t_f64, const void *spec, void *out, bool out_f64,
+                        const void *tw_half, const void *twist, double scale, const double *mu,
+                        hipStream_t st);
+
+// Column pass along y (axis 1) or z (axis 2), forward or inverse, in place,
+// main and nyq together. tw_full is the length-N table.
+hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,
+                      hipStream_t st);
+
+// Plain multiply-accumulate A (+)= G^ S over one slice (first: A = G^ S).
+hipError_t launch_mac_plain(int n, bool t_f64, void *A, const void *S, const void *ghat, bool first,
+                            hipStream_t st);
+
+// Fused z pass for FP32: for each column of the y-transformed slices,
+// forward z transform of every slice k < kcount[b], multiply by G^_{k,b},
+// compensated sum over k, inverse z transform, store to acc[b].
+struct FusedArgs {
+    const void *spec;        // K slices, stride spec_elems(n)
+    int64_t spec_stride;
+    const void *ghat;        // slice k band b at ghat + (k*B + b)*oct_stride
+    int64_t oct_stride;
+    int32_t K, B;            // slices, total bands in ghat layout
+    int32_t band0, nband;    // bands handled by this launch (nband 1 or 2)
+    int32_t kcount[2];       // slices with nonzero kernel, per handled band
+    void *acc;               // band b at acc + (b - band0)*spec_stride ... see launcher
+    int64_t acc_stride;
+    int32_t zero_dc;         // 1: drop the (0,0,0) bin (FP64 mean added later)
+    int32_t kahan;           // 1: compensated sum
+};
+hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);
+
+// Shell kernel builder (FP64): G_k on the octant, mirrored into a full N^3
+// FP64 grid.
+struct BuildArgs {
+    double *grid;             // N^3 FP64
+    int32_t n, m;
+    double l, h;
+    double t_lo, t_hi;        // thresholds of [r_k, r_{k+1})
+    double r_lo, r_hi;
+    int32_t images;           // |u_d| <= images
+    int32_t self_pair;        // 1: the self pair is replaced (r_0 == 0)
+    double self_val;          // added at cell 0 when this is slice 0 and self_pair
+    int32_t kind;
+    double a, s, p, c, cut, pref;
+};
+hipError_t launch_greens_build(const BuildArgs &a, hipStream_t st);
+
+// Fold the FP64 spectrum of G_k to the octant store of the plan precision,
+// scaled by (conserve ? target / (l^3 Re G^(0)) : 1); writes G^(0) (after
+// scaling) to *dc and folds max|Im|, max|Re| into maxima[0..1] (atomic).
+hipError_t launch_greens_fold(int n, const void *spec64, void *oct, bool oct_f64, int conserve,
+                              double target_over_l3, double *dc, unsigned long long *maxima,
+                              hipStream_t st);
+
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
+hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
+hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
+                          bool lum_f64, int64_t n_cells, hipStream_t st);
+// mu[b] = sum_k g0[k*B + b] * sum_w dcpart[k*W + w] / n3, for b < B, k < K
+hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
+                            double inv_n3, double *mu, hipStream_t st);
+
+}  // namespace lc

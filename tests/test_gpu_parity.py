@@ -1,0 +1,120 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances: FP64 path e_max <= 1e-12 (normwise max relative error);
+FP32 paths e_rms <= 1e-5 (normwise rms relative error), as fixed for the
+two arithmetic forms.
+"""
+import numpy as np
+import pytest
+
+import lc_inputs as li
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lc():
+    import paper_1502_02294_amd as lc
+    return lc
+
+
+def _box(n, L, radii, m, bands, sources, conserve=0):
+    return li.Box(n=n, box=L, radii=np.asarray(radii, dtype=np.float64), supersample=m,
+                  bands=bands, sources=sources, conserve=conserve)
+
+
+def _run_gpu(box, precision, as_points=True, out_dtype=None):
+    lc = _lc()
+    plan = lc.Plan([box], precision=precision)
+    plan.build_all()
+    keep = []
+    for k, (cells, lum) in enumerate(box.sources):
+        if as_points:
+            c = torch.from_numpy(np.asarray(cells, np.int64)).cuda()
+            v = torch.from_numpy(np.asarray(lum, np.float64)).cuda()
+            keep.append(plan.push_points(0, k, c, v))
+        else:
+            g = torch.from_numpy(oracle.deposit(box.n, cells, lum).ravel()).cuda()
+            if precision != lc.LC_PREC_FP64:
+                g = g.float()
+            keep.append(plan.push_grid(0, k, g))
+    outs = []
+    for b in range(len(box.bands)):
+        outs.append(plan.field(0, b, dtype=out_dtype).double().cpu().numpy())
+    torch.cuda.synchronize()
+    dcs = [plan.greens_dc(0, b) for b in range(len(box.bands))]
+    ims = [plan.greens_imag_ratio(0, b) for b in range(len(box.bands))]
+    plan.close()
+    return outs, dcs, ims
+
+
+def _oracle_full(box, band=0):
+    G = oracle.build_G(box.n, box.box, box.radii, box.supersample, box.bands[band], box.conserve)
+    J = oracle.field_direct(G, box.sources, np.arange(box.n ** 3)).reshape(box.n, box.n, box.n)
+    return J, G
+
+
+def test_cfg1_fp64_full_grid():
+    w = li.cfg1()
+    b = w.boxes[0]
+    print("case cfg1 fp64", flush=True)
+    (J,), (dc,), (im,) = _run_gpu(b, _lc().LC_PREC_FP64)
+    Jr, G = _oracle_full(b)
+    e_max, e_rms = oracle.rel_errors(J, Jr)
+    print(f"cfg1 fp64 e_max={e_max:.3e} e_rms={e_rms:.3e} imag={im:.2e}")
+    assert e_max <= 1e-12
+    np.testing.assert_allclose(dc, G.sum(axis=(1, 2, 3)), rtol=1e-13)
+    assert im <= 1e-14
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 48, 96])
+def test_small_grids_fp64_all_schedules(n):
+    """Every radix schedule (x pass N/2, y/z passes N) against route D."""
+    L = 1.25 * n
+    K = 3
+    radii = np.linspace(0.0, 0.95 * L, K + 1)
+    at = li.Atten(kind=1, a=1.7, s=0.7 * L / li.LW_X0, p=0.68, c=0.7)
+    srcs = [li.random_sources([n, k], n, 5 + 7 * k) for k in range(K)]
+    b = _box(n, L, radii, 2, [at], srcs)
+    print(f"case small n={n}", flush=True)
+    (J,), (dc,), (im,) = _run_gpu(b, _lc().LC_PREC_FP64)
+    Jr, G = _oracle_full(b)
+    e_max, e_rms = oracle.rel_errors(J, Jr)
+    print(f"n={n} e_max={e_max:.3e}")
+    assert e_max <= 1e-12
+    np.testing.assert_allclose(dc, G.sum(axis=(1, 2, 3)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_plain"])
+def test_cfg1_fp32_forms(prec):
+    lc = _lc()
+    w = li.cfg1()
+    b = w.boxes[0]
+    p = lc.LC_PREC_FP32 if prec == "fp32" else lc.LC_PREC_FP32_PLAIN
+    print(f"case cfg1 {prec}", flush=True)
+    (J,), _, _ = _run_gpu(b, p, as_points=False)
+    Jr, _ = _oracle_full(b)
+    e_max, e_rms = oracle.rel_errors(J, Jr)
+    print(f"cfg1 {prec} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    assert e_rms <= 1e-5
+    assert e_max <= 1e-4
+
+
+def test_two_bands_fp32_and_fp64():
+    """Two radial factors sharing the sources, both forms."""
+    lc = _lc()
+    n, L, K = 32, 25.0, 6
+    radii = np.linspace(0.0, 24.0, K + 1)
+    bands = [li.lw_band(20.0), li.lw_band(11.0)]
+    srcs = [li.random_sources([77, k], n, 50) for k in range(K)]
+    b = _box(n, L, radii, 2, bands, srcs)
+    for prec, tol in ((lc.LC_PREC_FP64, 1e-12), (lc.LC_PREC_FP32, 1e-5)):
+        print(f"case two bands prec={prec}", flush=True)
+        Js, _, _ = _run_gpu(b, prec)
+        for band in range(2):
+            Jr, _ = _oracle_full(b, band)
+            e_max, e_rms = oracle.rel_errors(Js[band], Jr)
+            print(f"prec={prec} band={band} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+            assert (e_max if prec == lc.LC_PREC_FP64 else e_rms) <= tol
