@@ -198,6 +198,28 @@ int lc_greens_imag_ratio(lc_plan_t *plan, int32_t box, int32_t band, double *rat
  * memory dc[K]; synchronises the stream. */
 int lc_greens_dc(lc_plan_t *plan, int32_t box, int32_t band, double *dc);
 
+/* Kernels of the path, for lc_time_kernel. */
+typedef enum {
+    LC_KERNEL_X_FWD = 0,      /* forward x pass of one slice (reads the source grid) */
+    LC_KERNEL_COL_Y_FWD = 1,  /* forward y pass of one slice, in place               */
+    LC_KERNEL_COL_Z_FWD = 2,  /* forward z pass of one slice (unfused forms)          */
+    LC_KERNEL_FUSED_Z = 3,    /* fused z pass + slice sum over all slices (FP32 form)  */
+    LC_KERNEL_MAC = 4,        /* plain multiply-accumulate of one slice (unfused)     */
+    LC_KERNEL_COL_Z_INV = 5,  /* inverse z pass of one band (unfused forms)           */
+    LC_KERNEL_COL_Y_INV = 6,  /* inverse y pass of one band                           */
+    LC_KERNEL_X_INV = 7       /* inverse x pass + epilogue of one band                */
+} lc_kernel_id;
+
+/* Diagnostic: launch one kernel of the path `reps` times back to back on
+ * the plan's stream, on the buffers of slice 0 / band 0 of `box`, and
+ * return the mean duration per launch measured with HIP events recorded on
+ * that stream. Kernels are built and slices pushed beforehand; the source
+ * of LC_KERNEL_X_FWD is a zeroed FP64 or FP32 grid (plan precision) in
+ * the workspace scratch and the output of LC_KERNEL_X_INV goes there too.
+ * Synchronises the stream. Errors: LC_EINVAL (bad id, reps < 1, kernel
+ * not part of this plan's form), LC_ESTATE (kernels not built). */
+int lc_time_kernel(lc_plan_t *plan, int32_t box, int32_t kernel, int32_t reps, double *avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

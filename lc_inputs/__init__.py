@@ -221,3 +221,12 @@ def sublattice_cells(n: int, stride: int, offset: int = 0) -> np.ndarray:
     idx = np.arange(offset, n, stride, dtype=np.int64)
     i, j, k = np.meshgrid(idx, idx, idx, indexing="ij")
     return ((i * n + j) * n + k).ravel()
+
+
+def dense_grid(n: int, cells: np.ndarray, lum: np.ndarray, dtype=np.float64) -> np.ndarray:
+    """The per-cell luminosity field of a point list (several sources in a
+    cell add): the dense source grid of one slice, as the input format of a
+    simulation that stores its sources on the mesh."""
+    g = np.bincount(np.asarray(cells, np.int64), weights=np.asarray(lum, np.float64),
+                    minlength=n ** 3)
+    return g.astype(dtype, copy=False)

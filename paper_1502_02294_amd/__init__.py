@@ -27,7 +27,11 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", 
                 -5: "LC_EUNSUPPORTED", -6: "LC_ENONFINITE"}
 
 EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_field",
-            "lc_step", "lc_destroy", "lc_last_error", "lc_greens_imag_ratio", "lc_greens_dc"]
+            "lc_step", "lc_destroy", "lc_last_error", "lc_greens_imag_ratio", "lc_greens_dc",
+            "lc_time_kernel"]
+
+(LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
+ LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV) = range(8)
 
 
 class lc_box_desc(C.Structure):
@@ -86,8 +90,9 @@ def load():
     L.lc_last_error.restype = C.c_char_p
     L.lc_greens_imag_ratio.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.lc_greens_dc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.lc_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_field", "lc_step",
-                 "lc_greens_imag_ratio", "lc_greens_dc"]:
+                 "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -167,7 +172,10 @@ def lc_destroy(plan):
 
 class Plan:
     """A plan over one or more boxes, with its workspace in a torch uint8
-    tensor on the current device and work on the current torch stream.
+    tensor on the current device. The library's work runs on a stream of
+    the plan's own (default priority; the legacy default stream cannot be
+    captured into a graph); every call first makes that stream wait for the
+    caller's current stream and makes the current stream wait for it after.
 
     boxes: sequence of objects with n, box, radii, bands (list), supersample,
     conserve (e.g. lc_inputs.Box).
@@ -194,15 +202,25 @@ class Plan:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._enter()
         desc, arr2 = make_plan_desc(descs, precision, self.stream.cuda_stream, aligned, nbytes,
                                     1 if use_graph else 0)
         self._keep.append(arr2)
         self.handle = lc_plan(desc)
+        self._leave()
+
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def build_greens(self, box: int = 0, band: int = 0, atten=None):
         at = atten if atten is not None else self.boxes[box].bands[band]
+        self._enter()
         lc_build_greens(self.handle, box, band, make_atten(at))
+        self._leave()
 
     def build_all(self):
         for bi, b in enumerate(self.boxes):
@@ -217,7 +235,9 @@ class Plan:
             raise TypeError("source grid must be float32 or float64")
         mem = LC_MEM_DEVICE if t.is_cuda else LC_MEM_HOST
         src = lc_sources(0, dt, mem, 0, t.data_ptr(), 0, None, None)
+        self._enter()
         lc_push_sources(self.handle, box, slice_, src)
+        self._leave()
         return t  # caller keeps it alive until the stream reaches the call
 
     def push_points(self, box: int, slice_: int, cells, lum):
@@ -229,7 +249,9 @@ class Plan:
         mem = LC_MEM_DEVICE if c.is_cuda else LC_MEM_HOST
         src = lc_sources(1, dt, mem, 0, None, int(c.numel()), c.data_ptr() if c.numel() else None,
                          v.data_ptr() if v.numel() else None)
+        self._enter()
         lc_push_sources(self.handle, box, slice_, src)
+        self._leave()
         return c, v
 
     def field(self, box: int = 0, band: int = 0, dtype=None, out=None):
@@ -240,7 +262,9 @@ class Plan:
             out = torch.empty((n, n, n), dtype=dtype, device=self.device)
         dt = LC_F64 if out.dtype == torch.float64 else LC_F32
         mem = LC_MEM_DEVICE if out.is_cuda else LC_MEM_HOST
+        self._enter()
         lc_field(self.handle, box, band, [out.data_ptr()], dt, mem)
+        self._leave()
         return out
 
     def greens_dc(self, box: int = 0, band: int = 0):
@@ -253,6 +277,28 @@ class Plan:
         v = C.c_double()
         _check(load().lc_greens_imag_ratio(self.handle, box, band, C.byref(v)))
         return float(v.value)
+
+    def time_kernel(self, kernel: int, box: int = 0, reps: int = 10) -> float:
+        """Mean milliseconds per launch of one kernel of the path (HIP events)."""
+        v = C.c_double()
+        self._enter()
+        _check(load().lc_time_kernel(self.handle, box, kernel, reps, C.byref(v)))
+        self._leave()
+        return float(v.value)
+
+    def step(self, grids, outs, dtype=None):
+        """One whole step (lc_step): push every slice of every box from dense
+        device grids (box-major list) and evaluate every band into outs
+        (box-major, band; device tensors of one dtype)."""
+        torch = self.torch
+        srcs = []
+        for g in grids:
+            dt = LC_F64 if g.dtype == torch.float64 else LC_F32
+            srcs.append(lc_sources(0, dt, LC_MEM_DEVICE, 0, g.data_ptr(), 0, None, None))
+        odt = LC_F64 if outs[0].dtype == torch.float64 else LC_F32
+        self._enter()
+        lc_step(self.handle, srcs, [o.data_ptr() for o in outs], odt)
+        self._leave()
 
     def close(self):
         if getattr(self, "handle", None):

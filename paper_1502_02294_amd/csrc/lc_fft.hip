@@ -19,42 +19,51 @@ namespace lc {
 template <typename T, typename TIN, int N, bool DC>
 __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
     const TIN *__restrict__ in, cx<T> *__restrict__ mainp, cx<T> *__restrict__ nyq, int64_t n_rows,
-    const cx<T> *__restrict__ tw, const cx<T> *__restrict__ twist, double *__restrict__ dcpart) {
+    const cx<T> *__restrict__ tw_g, const cx<T> *__restrict__ twist_g, double *__restrict__ dcpart) {
     constexpr int L = N / 2;
     using SH = RowShape<T, L>;
-    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD;
+    using EN = Engine<T, L, true>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD, E = EN::E;
     __shared__ cx<T> lds[RPW * LS];
+    __shared__ cx<T> tws[L];
+    __shared__ cx<T> twst[L];
     __shared__ double red[NT / 64];
-
+    for (int i = threadIdx.x; i < L; i += NT) {
+        tws[i] = tw_g[i];
+        twst[i] = twist_g[i];
+    }
     const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    const int64_t row = row0 + line;
+    const bool active = row < n_rows;
     double dsum = 0.0;
-    // coalesced load of RPW consecutive rows (one contiguous block)
-    for (int e = threadIdx.x; e < RPW * L; e += NT) {
-        const int rr = e / L, nn = e % L;
-        if (row0 + rr < n_rows) {
-            const int64_t g = (row0 + rr) * N + 2 * nn;
-            const TIN a = in[g], b = in[g + 1];
-            lds[rr * LS + nn] = mk((T)a, (T)b);
+    cx<T> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = EN::in_pos(t, e);
+        if (active) {
+            const TIN a = in[row * N + 2 * p], b = in[row * N + 2 * p + 1];
+            x[e] = mk((T)a, (T)b);
             if (DC) dsum += (double)a + (double)b;
+        } else {
+            x[e] = mk((T)0, (T)0);
         }
     }
+    EN::run(x, lds, line * LS, 1, t, tws);
     __syncthreads();
-    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const bool active = (row0 + line) < n_rows;
-    fft_lds<T, L, true>(lds, line * LS, 1, t, active, tw);
-
+    cx<T> *z = lds + line * LS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[EN::out_pos(t, e)] = x[e];
+    __syncthreads();
     if (active) {
-        const int64_t row = row0 + line;
-        const cx<T> *z = lds + line * LS;
         for (int p = t; p <= L / 2; p += TPL) {
             const cx<T> A = z[p], B = z[(L - p) % L];
-            const cx<T> E = mk((A.x + B.x) * (T)0.5, (A.y - B.y) * (T)0.5);
-            // O = (A - conj B) / (2i) = ((A.y + B.y), -(A.x - B.x)) / 2
+            const cx<T> Ev = mk((A.x + B.x) * (T)0.5, (A.y - B.y) * (T)0.5);
+            // O = (A - conj B) / (2i)
             const cx<T> O = mk((A.y + B.y) * (T)0.5, (B.x - A.x) * (T)0.5);
-            const cx<T> WO = cmul(twist[p], O);
-            const cx<T> Xp = E + WO;
-            const cx<T> Xm = conj(E - WO);
-            mainp[row * L + p] = Xp;
+            const cx<T> WO = cmul(twst[p], O);
+            mainp[row * L + p] = Ev + WO;
+            const cx<T> Xm = conj(Ev - WO);
             if (p == 0) nyq[row] = Xm;
             else if (p != L - p) mainp[row * L + (L - p)] = Xm;
         }
@@ -78,65 +87,114 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
 template <typename T, typename TOUT, int N>
 __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_inv_kernel(
     const cx<T> *__restrict__ mainp, const cx<T> *__restrict__ nyq, TOUT *__restrict__ out,
-    int64_t n_rows, const cx<T> *__restrict__ tw, const cx<T> *__restrict__ twist, double scale,
+    int64_t n_rows, const cx<T> *__restrict__ tw_g, const cx<T> *__restrict__ twist_g, double scale,
     const double *__restrict__ mu) {
     constexpr int L = N / 2;
     using SH = RowShape<T, L>;
-    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD;
+    using EN = Engine<T, L, false>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD, E = EN::E;
     __shared__ cx<T> lds[RPW * LS];
-
-    const int64_t row0 = (int64_t)blockIdx.x * RPW;
-    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
-    const bool active = (row0 + line) < n_rows;
-    if (active) {
-        const int64_t row = row0 + line;
-        cx<T> *z = lds + line * LS;
-        for (int p = t; p <= L / 2; p += TPL) {
-            if (p == 0) {
-                const T x0 = mainp[row * L].x, xl = nyq[row].x;
-                z[0] = mk(x0 + xl, x0 - xl);
-            } else {
-                const cx<T> Xp = mainp[row * L + p], Xm = mainp[row * L + (L - p)];
-                const cx<T> Ep = Xp + conj(Xm);
-                const cx<T> D = Xp - conj(Xm);
-                const cx<T> Op = cmul(D, conj(twist[p]));
-                // Z[p] = Ep + i Op ; Z[L-p] = conj(Ep) + i conj(Op)
-                z[p] = mk(Ep.x - Op.y, Ep.y + Op.x);
-                if (p != L - p) z[L - p] = mk(Ep.x + Op.y, Op.x - Ep.y);
-            }
-        }
+    __shared__ cx<T> tws[L];
+    __shared__ cx<T> twst[L];
+    for (int i = threadIdx.x; i < L; i += NT) {
+        tws[i] = tw_g[i];
+        twst[i] = twist_g[i];
     }
     __syncthreads();
-    fft_lds<T, L, false>(lds, line * LS, 1, t, active, tw);
-    const double m = mu ? *mu : 0.0;
-    for (int e = threadIdx.x; e < RPW * L; e += NT) {
-        const int rr = e / L, nn = e % L;
-        if (row0 + rr < n_rows) {
-            const cx<T> v = lds[rr * LS + nn];
-            const int64_t g = (row0 + rr) * N + 2 * nn;
-            out[g] = (TOUT)((double)v.x * scale + m);
-            out[g + 1] = (TOUT)((double)v.y * scale + m);
+    const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    const int64_t row = row0 + line;
+    const bool active = row < n_rows;
+    cx<T> x[E];
+    // Z[p] = E'_p + i O'_p with E'_p = X[p] + conj X[L-p],
+    // O'_p = (X[p] - conj X[L-p]) conj(W^p); at p = 0 the real parts of X[0], X[L]
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = EN::in_pos(t, e);
+        if (!active) {
+            x[e] = mk((T)0, (T)0);
+        } else if (p == 0) {
+            const T x0 = mainp[row * L].x, xl = nyq[row].x;
+            x[e] = mk(x0 + xl, x0 - xl);
+        } else {
+            const cx<T> Xp = mainp[row * L + p], Xm = mainp[row * L + (L - p)];
+            const cx<T> Ep = Xp + conj(Xm);
+            const cx<T> Op = cmul(Xp - conj(Xm), conj(twst[p]));
+            x[e] = mk(Ep.x - Op.y, Ep.y + Op.x);
+        }
+    }
+    EN::run(x, lds, line * LS, 1, t, tws);
+    if (active) {
+        const double m = mu ? *mu : 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t g = row * N + 2 * EN::out_pos(t, e);
+            out[g] = (TOUT)((double)x[e].x * scale + m);
+            out[g + 1] = (TOUT)((double)x[e].y * scale + m);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// column passes (y or z), in place; grid = main WGs then nyq WGs
+// column passes (y or z), in place; grid = main WGs then nyq WGs.
+// Lanes walk the columns (col_stride 1) or, for row-contiguous sets, the
+// rows of a column, so that global accesses stay coalesced either way.
+// With COMBINE (inverse y pass of a fused FP32 accumulator) the second part
+// of a tile that the persistent fused pass split between two workgroups is
+// added while loading: element (z, y=q, p) belongs to fused tile
+// (q*H + p) / cpw_z (main) or tiles_main + q / cpw_z (nyq), at row z.
 // ---------------------------------------------------------------------------
-template <typename T, int L, bool FWD>
-__global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(cx<T> *data, ColSet s0, ColSet s1,
-                                                                const cx<T> *__restrict__ tw) {
+template <int CPW, int TPL>
+__device__ __forceinline__ void col_lane(bool rowfast, int &c, int &t) {
+    if (rowfast) { c = threadIdx.x / TPL; t = threadIdx.x % TPL; }
+    else { c = threadIdx.x % CPW; t = threadIdx.x / CPW; }
+}
+
+template <typename T, int L, bool FWD, bool COMBINE>
+__global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(
+    cx<T> *data, ColSet s0, ColSet s1, const cx<T> *__restrict__ tw_g, const int *__restrict__ tab,
+    const cx<T> *__restrict__ part, int64_t tiles_main, int cpw_z) {
     using SH = ColShape<T, L>;
-    constexpr int CPW = SH::CPW, NT = SH::NT, PAD = SH::PAD, ES = CPW + PAD;
+    using EN = Engine<T, L, FWD>;
+    constexpr int CPW = SH::CPW, NT = SH::NT, ES = CPW + SH::PAD, E = EN::E, TPL = SH::TPL;
     __shared__ cx<T> lds[L * ES];
+    __shared__ cx<T> tws[L];
+    for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
     const bool first = (int)blockIdx.x < s0.n_wgs;
     const ColSet &s = first ? s0 : s1;
     const int64_t col0 = (int64_t)(first ? blockIdx.x : blockIdx.x - s0.n_wgs) * CPW;
-    tile_load<T, L, CPW, NT, PAD>(lds, data, s, col0);
-    __syncthreads();
-    const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
-    fft_lds<T, L, FWD>(lds, c, ES, t, true, tw);
-    tile_store<T, L, CPW, NT, PAD>(data, lds, s, col0);
+    int c, t;
+    col_lane<CPW, TPL>(s.rowfast, c, t);
+    const int64_t col = col0 + c;
+    const bool ok = col < s.n_cols;
+    const int64_t base = ok ? col_base(s, col) : 0;
+    cx<T> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = EN::in_pos(t, e);
+        x[e] = ok ? data[base + j * s.row_stride] : mk((T)0, (T)0);
+        if constexpr (COMBINE) {
+            if (ok) {
+                int zt, zc, z;
+                if (first) {
+                    const int H = L / 2;
+                    z = (int)(col / H);
+                    const int q = j * H + (int)(col % H);
+                    zt = q / cpw_z; zc = q % cpw_z;
+                } else {
+                    z = (int)col;
+                    zt = (int)(tiles_main + j / cpw_z); zc = j % cpw_z;
+                }
+                const int w = tab[zt];
+                if (w >= 0) x[e] = x[e] + part[((int64_t)w * L + z) * cpw_z + zc];
+            }
+        }
+    }
+    EN::run(x, lds, c, ES, t, tws);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) data[base + EN::out_pos(t, e) * s.row_stride] = x[e];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -265,12 +323,34 @@ static hipError_t col_t(int axis, bool fwd, void *spec, const void *tw, hipStrea
     col_sets<T, N>(axis, s0, s1);
     const int wgs = s0.n_wgs + s1.n_wgs;
     if (fwd)
-        hipLaunchKernelGGL((col_kernel<T, N, true>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec, s0,
-                           s1, (const cx<T> *)tw);
+        hipLaunchKernelGGL((col_kernel<T, N, true, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec,
+                           s0, s1, (const cx<T> *)tw, nullptr, nullptr, (int64_t)0, 1);
     else
-        hipLaunchKernelGGL((col_kernel<T, N, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec, s0,
-                           s1, (const cx<T> *)tw);
+        hipLaunchKernelGGL((col_kernel<T, N, false, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec,
+                           s0, s1, (const cx<T> *)tw, nullptr, nullptr, (int64_t)0, 1);
     return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_comb_t(void *spec, const void *tw, const int *tab, const void *part, hipStream_t st) {
+    using SH = ColShape<float, N>;
+    ColSet s0, s1;
+    col_sets<float, N>(1, s0, s1);
+    // the fused pass tiles its N*H main columns by ColShape<float, N>::CPW
+    const int cpw_z = SH::CPW;
+    const int64_t tiles_main = ((int64_t)N * (N / 2) + cpw_z - 1) / cpw_z;
+    hipLaunchKernelGGL((col_kernel<float, N, false, true>), dim3(s0.n_wgs + s1.n_wgs), dim3(SH::NT), 0, st,
+                       (cx<float> *)spec, s0, s1, (const cx<float> *)tw, tab, (const cx<float> *)part,
+                       tiles_main, cpw_z);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_y_inv_combine(int n, void *spec, const void *tw_full, const int *split_tab,
+                                    const void *part, hipStream_t st) {
+#define X_(N) return col_comb_t<N>(spec, tw_full, split_tab, part, st);
+    LC_DISPATCH_N(n, X_)
+#undef X_
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,

@@ -138,39 +138,63 @@ template <int R, bool FWD, typename T> __device__ __forceinline__ void dft(cx<T>
 }
 
 // ---- radix schedules ----------------------------------------------------------
-// Forward passes use R[0..NP-1]; the inverse runs them reversed, so the last
+// Forward passes use r(0..NP-1); the inverse runs them reversed, so the last
 // forward pass and the first inverse pass share the same element-to-thread
-// placement (used by the fused slice-sum pass).
+// placement (used by the fused slice-sum pass). TPL threads work on one line;
+// the first and the last pass give every thread whole butterflies, so each
+// thread holds E = L / TPL elements in registers before the first pass and
+// after the last one (middle passes go through LDS).
 
 template <int L> struct Sched;
-#define LC_SCHED(L_, NP_, R0, R1, R2, TPL_)                                   \
-    template <> struct Sched<L_> {                                            \
-        static constexpr int NP = NP_;                                        \
-        static constexpr int TPL = TPL_;                                      \
-        static constexpr int r(int i) { return i == 0 ? R0 : i == 1 ? R1 : R2; } \
+#define LC_SCHED(L_, NP_, R0, R1, R2, R3, TPL_)                                           \
+    template <> struct Sched<L_> {                                                        \
+        static constexpr int NP = NP_;                                                    \
+        static constexpr int TPL = TPL_;                                                  \
+        static constexpr int r(int i) { return i == 0 ? R0 : i == 1 ? R1 : i == 2 ? R2 : R3; } \
     };
-LC_SCHED(4, 1, 4, 0, 0, 1)
-LC_SCHED(6, 2, 3, 2, 0, 1)
-LC_SCHED(8, 1, 8, 0, 0, 1)
-LC_SCHED(12, 2, 4, 3, 0, 1)
-LC_SCHED(16, 1, 16, 0, 0, 1)
-LC_SCHED(24, 2, 8, 3, 0, 2)
-LC_SCHED(32, 2, 8, 4, 0, 2)
-LC_SCHED(48, 2, 16, 3, 0, 4)
-LC_SCHED(64, 2, 16, 4, 0, 4)
-LC_SCHED(96, 3, 8, 4, 3, 8)
-LC_SCHED(128, 2, 16, 8, 0, 8)
-LC_SCHED(192, 3, 16, 4, 3, 16)
-LC_SCHED(256, 2, 16, 16, 0, 16)
-LC_SCHED(384, 3, 16, 8, 3, 32)
-LC_SCHED(512, 3, 16, 8, 4, 32)
+LC_SCHED(4, 1, 4, 0, 0, 0, 1)
+LC_SCHED(6, 2, 3, 2, 0, 0, 1)
+LC_SCHED(8, 1, 8, 0, 0, 0, 1)
+LC_SCHED(12, 2, 4, 3, 0, 0, 1)
+LC_SCHED(16, 1, 16, 0, 0, 0, 1)
+LC_SCHED(24, 2, 8, 3, 0, 0, 1)
+LC_SCHED(32, 2, 8, 4, 0, 0, 2)
+LC_SCHED(48, 3, 4, 4, 3, 0, 4)
+LC_SCHED(64, 2, 16, 4, 0, 0, 4)
+LC_SCHED(96, 3, 4, 8, 3, 0, 8)
+LC_SCHED(128, 2, 16, 8, 0, 0, 8)
+LC_SCHED(192, 3, 4, 16, 3, 0, 16)
+LC_SCHED(256, 2, 16, 16, 0, 0, 16)
+LC_SCHED(384, 4, 4, 8, 4, 3, 32)
+LC_SCHED(512, 3, 16, 8, 4, 0, 32)
 #undef LC_SCHED
 
-template <int L, bool FWD> __device__ __host__ constexpr int pass_radix(int p) {
-    return FWD ? Sched<L>::r(p) : Sched<L>::r(Sched<L>::NP - 1 - p);
+// Schedules with 8 elements per thread for the fused slice-sum pass, whose
+// per-element accumulators make register space scarce.
+template <int L> struct Sched8;
+#define LC_SCHED8(L_, NP_, R0, R1, R2, R3, TPL_)                                          \
+    template <> struct Sched8<L_> {                                                       \
+        static constexpr int NP = NP_;                                                    \
+        static constexpr int TPL = TPL_;                                                  \
+        static constexpr int r(int i) { return i == 0 ? R0 : i == 1 ? R1 : i == 2 ? R2 : R3; } \
+    };
+LC_SCHED8(64, 2, 8, 8, 0, 0, 8)
+LC_SCHED8(128, 3, 8, 2, 8, 0, 16)
+LC_SCHED8(256, 3, 8, 4, 8, 0, 32)
+LC_SCHED8(512, 3, 8, 8, 8, 0, 64)
+#undef LC_SCHED8
+
+template <int L, bool FWD, typename S = Sched<L>> __device__ __host__ constexpr int pass_radix(int p) {
+    return FWD ? S::r(p) : S::r(S::NP - 1 - p);
 }
 
-// ---- one Stockham pass, split in a read half and a write half ---------------
+template <int L, bool FWD, typename S = Sched<L>> __device__ __host__ constexpr int ns_before(int p) {
+    int ns = 1;
+    for (int i = 0; i < p; ++i) ns *= pass_radix<L, FWD, S>(i);
+    return ns;
+}
+
+// ---- one Stockham pass ----------------------------------------------------------
 // Line elements live in LDS at lds[lbase + i*es]; thread t in [0, TPL).
 
 template <typename T, int L, int R, int NS, int TPL, bool FWD>
@@ -179,24 +203,27 @@ struct Pass {
     static constexpr int BPT = (NB + TPL - 1) / TPL;
     static constexpr bool EVEN = (NB % TPL) == 0;
 
+    __device__ __forceinline__ static void twiddle(cx<T> *v, int b, const cx<T> *tw) {
+        if constexpr (NS > 1) {
+            const int base = (b % NS) * (L / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[base * r];
+                if (!FWD) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+    }
     // read, twiddle and transform this thread's butterflies into v
     __device__ __forceinline__ static void read(const cx<T> *lds, int lbase, int es, int t,
-                                                const cx<T> *__restrict__ tw, cx<T> (&v)[BPT][R]) {
+                                                const cx<T> *tw, cx<T> (&v)[BPT][R]) {
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
             const int b = t + i * TPL;
             if (EVEN || b < NB) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[i][r] = lds[lbase + (b + r * NB) * es];
-                if constexpr (NS > 1) {
-                    const int base = (b % NS) * (L / (NS * R));
-#pragma unroll
-                    for (int r = 1; r < R; ++r) {
-                        cx<T> w = tw[base * r];
-                        if (!FWD) w.y = -w.y;
-                        v[i][r] = cmul(v[i][r], w);
-                    }
-                }
+                twiddle(v[i], b, tw);
                 dft<R, FWD>(v[i]);
             }
         }
@@ -213,42 +240,95 @@ struct Pass {
             }
         }
     }
-    // position (row along the line) of element v[i][r] after the write
+    // line position of input r of butterfly i of thread t
+    __device__ __forceinline__ static int in_pos(int t, int i, int r) { return t + i * TPL + r * NB; }
+    // line position of output r of butterfly i of thread t (after write)
     __device__ __forceinline__ static int out_pos(int t, int i, int r) {
         const int b = t + i * TPL;
         return (b / NS) * NS * R + (b % NS) + r * NS;
     }
 };
 
-template <int L, bool FWD> __device__ __host__ constexpr int ns_before(int p) {
-    int ns = 1;
-    for (int i = 0; i < p; ++i) ns *= pass_radix<L, FWD>(i);
-    return ns;
-}
-
-// Run passes [P, PEND) of the schedule from LDS to LDS. Every thread of the
-// workgroup must call this (it contains barriers).
-template <typename T, int L, bool FWD, int P, int PEND>
+// Run passes [P, PEND) of the schedule from LDS to LDS (barrier after each).
+// Every thread of the workgroup must call this.
+template <typename T, int L, bool FWD, int P, int PEND, typename S = Sched<L>>
 __device__ __forceinline__ void run_passes(cx<T> *lds, int lbase, int es, int t, bool active,
-                                           const cx<T> *__restrict__ tw) {
+                                           const cx<T> *tw) {
     if constexpr (P < PEND) {
-        constexpr int R = pass_radix<L, FWD>(P);
-        constexpr int NS = ns_before<L, FWD>(P);
-        using PS = Pass<T, L, R, NS, Sched<L>::TPL, FWD>;
+        constexpr int R = pass_radix<L, FWD, S>(P);
+        constexpr int NS = ns_before<L, FWD, S>(P);
+        using PS = Pass<T, L, R, NS, S::TPL, FWD>;
         cx<T> v[PS::BPT][R];
         if (active) PS::read(lds, lbase, es, t, tw, v);
         __syncthreads();
         if (active) PS::write(lds, lbase, es, t, v);
         __syncthreads();
-        run_passes<T, L, FWD, P + 1, PEND>(lds, lbase, es, t, active, tw);
+        run_passes<T, L, FWD, P + 1, PEND, S>(lds, lbase, es, t, active, tw);
     }
 }
 
-template <typename T, int L, bool FWD>
-__device__ __forceinline__ void fft_lds(cx<T> *lds, int lbase, int es, int t, bool active,
-                                        const cx<T> *__restrict__ tw) {
-    run_passes<T, L, FWD, 0, Sched<L>::NP>(lds, lbase, es, t, active, tw);
-}
+// Register-in / register-out transform of one line by TPL threads.
+// x[e] (e < E) holds, on entry, the first pass's inputs at line positions
+// in_pos(t, e) and, on return, the last pass's outputs at out_pos(t, e).
+template <typename T, int L, bool FWD, typename S = Sched<L>>
+struct Engine {
+    static constexpr int NP = S::NP;
+    static constexpr int TPL = S::TPL;
+    static constexpr int E = L / TPL;
+    static constexpr int R0 = pass_radix<L, FWD, S>(0);
+    static constexpr int RL = pass_radix<L, FWD, S>(NP - 1);
+    static constexpr int NSL = ns_before<L, FWD, S>(NP - 1);
+    using P0 = Pass<T, L, R0, 1, TPL, FWD>;
+    using PLs = Pass<T, L, RL, NSL, TPL, FWD>;
+    static_assert(P0::EVEN && PLs::EVEN, "first and last passes must give every thread whole butterflies");
+    static_assert(P0::BPT * R0 == E && PLs::BPT * RL == E, "element count per thread");
+
+    __device__ __forceinline__ static int in_pos(int t, int e) { return P0::in_pos(t, e / R0, e % R0); }
+    __device__ __forceinline__ static int out_pos(int t, int e) { return PLs::out_pos(t, e / RL, e % RL); }
+
+    // first pass in registers; with more than one pass its outputs go to LDS
+    // (after a barrier protecting earlier readers of the LDS line buffer)
+    __device__ __forceinline__ static void first(cx<T> (&x)[E], cx<T> *lds, int lbase, int es, int t) {
+#pragma unroll
+        for (int i = 0; i < P0::BPT; ++i) dft<R0, FWD>(x + i * R0);
+        if constexpr (NP > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < P0::BPT; ++i) {
+                const int o = (t + i * TPL) * R0;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) lds[lbase + (o + r) * es] = x[i * R0 + r];
+            }
+        }
+    }
+    // remaining passes; outputs in y (with NP == 1, y = x already transformed)
+    __device__ __forceinline__ static void rest(const cx<T> (&x)[E], cx<T> (&y)[E], cx<T> *lds, int lbase,
+                                                int es, int t, const cx<T> *tw) {
+        if constexpr (NP == 1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = x[e];
+        } else {
+            __syncthreads();
+            run_passes<T, L, FWD, 1, NP - 1, S>(lds, lbase, es, t, true, tw);
+#pragma unroll
+            for (int i = 0; i < PLs::BPT; ++i) {
+                const int b = t + i * TPL;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) y[i * RL + r] = lds[lbase + (b + r * PLs::NB) * es];
+                PLs::twiddle(y + i * RL, b, tw);
+                dft<RL, FWD>(y + i * RL);
+            }
+        }
+    }
+    __device__ __forceinline__ static void run(cx<T> (&x)[E], cx<T> *lds, int lbase, int es, int t,
+                                               const cx<T> *tw) {
+        first(x, lds, lbase, es, t);
+        cx<T> y[E];
+        rest(x, y, lds, lbase, es, t, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = y[e];
+    }
+};
 
 // Column sets: a batch of strided lines. Column c of the set has its element
 // at row j at  off + (c / W) * plane_stride + (c % W) * col_stride + j * row_stride.
@@ -312,12 +392,26 @@ __device__ __forceinline__ void tile_store(cx<T> *__restrict__ g, const cx<T> *l
     }
 }
 
-// Launch shape of the column passes for a line length L and element type.
+// Launch shape of the column passes for a line length L and element type:
+// CPW columns per workgroup (16 FP32 / 8 FP64 columns = 128-byte rows when
+// the lines are strided), TPL threads per column.
 template <typename T, int L> struct ColShape {
     static constexpr int TPL = Sched<L>::TPL;
-    static constexpr int NT = (sizeof(T) == 4 && L >= 384) ? 512 : 256;
-    static constexpr int CPW = NT / TPL;
-    static constexpr int PAD = (sizeof(T) == 4) ? 1 : 1;
+    static constexpr int CPW0 = sizeof(T) == 4 ? 16 : 8;
+    static constexpr int CPW = (CPW0 * TPL >= 64) ? CPW0 : 64 / TPL;   // at least one wave
+    static constexpr int NT = CPW * TPL;
+    static constexpr int PAD = 1;
+};
+
+// Launch shape of the fused slice-sum pass: schedule S, 16 columns per
+// workgroup (128-byte rows).
+template <int L, typename S> struct FusedShape {
+    static constexpr int TPL = S::TPL;
+    static constexpr int CPW = (16 * TPL >= 64) ? 16 : 64 / TPL;
+    static constexpr int NT = CPW * TPL;
+    static constexpr int PAD = 1;
+    // requested waves per SIMD: bounds the register budget (512 / WPE)
+    static constexpr int WPE = (L / TPL <= 8) ? 4 : 2;
 };
 
 // Launch shape of the row (x) passes for half-length L = N/2.

@@ -61,7 +61,16 @@ hipError_t launch_mac_plain(int n, bool t_f64, void *A, const void *S, const voi
 }
 
 // ---------------------------------------------------------------------------
-// fused z pass (FP32)
+// fused z pass (FP32), persistent with a balanced ("stream-K") partition
+//
+// The work is the sequence of (tile, slice) pairs, tile-major; tile t covers
+// CPW columns and its slices k < kmax. Workgroup w of P takes the pairs
+// [w W / P, (w+1) W / P), W = tiles * kmax, so every workgroup gets the same
+// number of slice-tiles up to one. Since W / P >= kmax, a tile is split
+// between at most two workgroups: the part starting at k = 0 is written to
+// the accumulator spectrum, the other part (starting at an interior k) to a
+// side buffer slot owned by the workgroup that computed it; the inverse y
+// pass adds it back when it loads the tile.
 // ---------------------------------------------------------------------------
 struct FusedDev {
     const cx<float> *spec;
@@ -71,151 +80,246 @@ struct FusedDev {
     int32_t B, band0, K0, K1;   // kcount of the two handled bands
     cx<float> *acc;
     int64_t acc_stride;
+    cx<float> *part;            // [band][P][L * CPW]
+    int64_t part_stride;
     int32_t zero_dc, kahan;
+    int32_t kmax, P;
+    int64_t W;
 };
 
-template <int L, int NB_>
-__global__ __launch_bounds__((ColShape<float, L>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
-                                                                         const cx<float> *__restrict__ tw) {
-    using SH = ColShape<float, L>;
-    constexpr int CPW = SH::CPW, NT = SH::NT, PAD = SH::PAD, ES = CPW + PAD, TPL = SH::TPL;
-    constexpr int NP = Sched<L>::NP;
-    constexpr int RL = pass_radix<L, true>(NP - 1);          // last forward radix
-    constexpr int NSL = ns_before<L, true>(NP - 1);           // = L / RL
-    using PL = Pass<float, L, RL, NSL, TPL, true>;            // last forward pass
-    using PI = Pass<float, L, RL, 1, TPL, false>;             // first inverse pass
-    constexpr int BPT = PL::BPT;
-    static_assert(NSL * RL == L, "schedule");
+template <int L, int NB_, typename S>
+__global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
+                                                                        const cx<float> *__restrict__ tw_g) {
+    using SH = FusedShape<L, S>;
+    using EF = Engine<float, L, true, S>;     // forward z transform
+    using EI = Engine<float, L, false, S>;    // inverse z transform
+    constexpr int CPW = SH::CPW, NT = SH::NT, ES = CPW + SH::PAD, E = EF::E;
+    static_assert(EI::E == E, "forward and inverse hold the same elements");
     __shared__ cx<float> lds[L * ES];
+    __shared__ cx<float> tws[L];
+    for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
 
-    const bool is_main = (int)blockIdx.x < s0.n_wgs;
-    const ColSet &s = is_main ? s0 : s1;
-    const int64_t col0 = (int64_t)(is_main ? blockIdx.x : blockIdx.x - s0.n_wgs) * CPW;
     const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
-    const int64_t col = col0 + c;
-    const bool col_ok = col < s.n_cols;
     const int H = L / 2, HP = H + 1;
+    const int w = blockIdx.x;
+    int64_t pos = (int64_t)w * a.W / a.P;
+    const int64_t end = (int64_t)(w + 1) * a.W / a.P;
 
-    // octant offset of this thread's elements (rows r = out_pos) in one G^ slice
-    int goff[BPT][RL];
-    {
-        int qf, p, base_main;
+    while (pos < end) {
+        const int64_t tile = pos / a.kmax;
+        const int k0 = (int)(pos % a.kmax);
+        const int k1 = (int)std::min<int64_t>(a.kmax, k0 + (end - pos));
+        pos += k1 - k0;
+
+        const bool is_main = tile < s0.n_wgs;
+        const ColSet &s = is_main ? s0 : s1;
+        const int64_t col0 = (is_main ? tile : tile - s0.n_wgs) * CPW;
+        const int64_t col = col0 + c;
+        const bool col_ok = col < s.n_cols;
+        // columns past the end compute on a valid column and are not stored
+        const int64_t ccol = col_ok ? col : col0;
+        const int64_t cbase = col_base(s, ccol);
+
+        // octant offset of this thread's column in one G^ slice; the row
+        // part (folded z frequency) is added per element
+        int gbase, grow;
         if (is_main) {
-            const int cc = col_ok ? (int)col : 0;
-            qf = fold(cc / H, L); p = cc % H;
-            base_main = 1;
+            const int cc = (int)ccol;
+            gbase = fold(cc / H, L) * H + cc % H;
+            grow = HP * H;
         } else {
-            qf = fold(col_ok ? (int)col : 0, L); p = H;
-            base_main = 0;
+            gbase = HP * HP * H + fold((int)ccol, L);
+            grow = HP;
         }
+
+        cx<float> sum[NB_][E], cmp[NB_][E];
 #pragma unroll
-        for (int i = 0; i < BPT; ++i)
+        for (int b = 0; b < NB_; ++b)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const int row = PL::out_pos(t, i, r);
-                const int rf = fold(row < L ? row : 0, L);
-                goff[i][r] = base_main ? (rf * HP + qf) * H + p
-                                       : HP * HP * H + rf * HP + qf;
+            for (int e = 0; e < E; ++e) { sum[b][e] = mk(0.f, 0.f); cmp[b][e] = mk(0.f, 0.f); }
+
+        // byte offsets of this thread's inputs within one slice spectrum and
+        // of its kernel values within one octant, off workgroup-uniform bases
+        // (a slice spectrum is below 4 GiB)
+        uint32_t xoff[E], goff[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            xoff[e] = (uint32_t)((cbase + (int64_t)EF::in_pos(t, e) * s.row_stride) * 8);
+            goff[e] = (uint32_t)((gbase + fold(EF::out_pos(t, e), L) * grow) * 4);
+        }
+        // first-pass inputs of slice k0
+        cx<float> x[E];
+        {
+            const char *src = (const char *)(a.spec + (int64_t)k0 * a.spec_stride);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = *(const cx<float> *)(src + xoff[e]);
+        }
+        for (int k = k0; k < k1; ++k) {
+            // kernel values of this slice, issued before the next prefetch; a
+            // band without a kernel for slice k reads a valid octant, weight 0
+            float g[NB_][E];
+#pragma unroll
+            for (int b = 0; b < NB_; ++b) {
+                const int kc = b == 0 ? a.K0 : a.K1;
+                const int kb = k < kc ? k : 0;
+                const float wgt = k < kc ? 1.f : 0.f;
+                const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
+#pragma unroll
+                for (int e = 0; e < E; ++e) g[b][e] = wgt * *(const float *)(gp + goff[e]);
             }
-    }
-
-    cx<float> sum[NB_][BPT][RL], cmp[NB_][BPT][RL];
+            EF::first(x, lds, c, ES, t);
+            cx<float> v[E];
+            if constexpr (EF::NP == 1) {
 #pragma unroll
-    for (int b = 0; b < NB_; ++b)
+                for (int e = 0; e < E; ++e) v[e] = x[e];
+            }
+            // x is free now: prefetch the next slice while the passes run
+            if (k + 1 < k1) {
+                const char *src = (const char *)(a.spec + (int64_t)(k + 1) * a.spec_stride);
 #pragma unroll
-        for (int i = 0; i < BPT; ++i)
+                for (int e = 0; e < E; ++e) x[e] = *(const cx<float> *)(src + xoff[e]);
+            }
+            if constexpr (EF::NP > 1) EF::rest(x, v, lds, c, ES, t, tws);
+            // compensated (Kahan) sum over slices
 #pragma unroll
-            for (int r = 0; r < RL; ++r) { sum[b][i][r] = mk(0.f, 0.f); cmp[b][i][r] = mk(0.f, 0.f); }
-
-    const int kmax = (NB_ > 1 && a.K1 > a.K0) ? a.K1 : a.K0;
-    for (int k = 0; k < kmax; ++k) {
-        tile_load<float, L, CPW, NT, PAD>(lds, a.spec + (int64_t)k * a.spec_stride, s, col0);
-        __syncthreads();
-        run_passes<float, L, true, 0, NP - 1>(lds, c, ES, t, true, tw);
-        cx<float> v[BPT][RL];
-        PL::read(lds, c, ES, t, tw, v);
-        __syncthreads();   // LDS free for the next slice
+            for (int b = 0; b < NB_; ++b)
 #pragma unroll
-        for (int b = 0; b < NB_; ++b) {
-            const int kc = b == 0 ? a.K0 : a.K1;
-            if (k >= kc) continue;
-            const float *g = a.ghat + ((int64_t)k * a.B + a.band0 + b) * a.oct_stride;
-#pragma unroll
-            for (int i = 0; i < BPT; ++i)
-#pragma unroll
-                for (int r = 0; r < RL; ++r) {
-                    const float gv = col_ok ? g[goff[i][r]] : 0.f;
-                    const float px = gv * v[i][r].x, py = gv * v[i][r].y;
-                    if (a.kahan) {
-                        const float yx = px - cmp[b][i][r].x, yy = py - cmp[b][i][r].y;
-                        const float tx = sum[b][i][r].x + yx, ty = sum[b][i][r].y + yy;
-                        cmp[b][i][r].x = (tx - sum[b][i][r].x) - yx;
-                        cmp[b][i][r].y = (ty - sum[b][i][r].y) - yy;
-                        sum[b][i][r].x = tx;
-                        sum[b][i][r].y = ty;
-                    } else {
-                        sum[b][i][r].x += px;
-                        sum[b][i][r].y += py;
-                    }
+                for (int e = 0; e < E; ++e) {
+                    const float gv = g[b][e];
+                    const float yx = gv * v[e].x - cmp[b][e].x, yy = gv * v[e].y - cmp[b][e].y;
+                    const float tx = sum[b][e].x + yx, ty = sum[b][e].y + yy;
+                    cmp[b][e].x = (tx - sum[b][e].x) - yx;
+                    cmp[b][e].y = (ty - sum[b][e].y) - yy;
+                    sum[b][e].x = tx;
+                    sum[b][e].y = ty;
                 }
         }
-    }
 
-    // the (0,0,0) bin: element row 0 of main column 0
-    const bool has_dc = a.zero_dc && is_main && col == 0;
-
+        // the (0,0,0) bin: row 0 of main column 0
+        const bool has_dc = a.zero_dc && is_main && col == 0;
+        const bool primary = k0 == 0;
 #pragma unroll
-    for (int b = 0; b < NB_; ++b) {
-        cx<float> v[BPT][RL];
+        for (int b = 0; b < NB_; ++b) {
+            cx<float> y[E];
 #pragma unroll
-        for (int i = 0; i < BPT; ++i)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                v[i][r] = a.kahan ? sum[b][i][r] - cmp[b][i][r] : sum[b][i][r];
-                if (has_dc && PL::out_pos(t, i, r) == 0) v[i][r] = mk(0.f, 0.f);
+            for (int e = 0; e < E; ++e) {
+                y[e] = sum[b][e] - cmp[b][e];
+                if (has_dc && EF::out_pos(t, e) == 0) y[e] = mk(0.f, 0.f);
             }
-        // first inverse pass straight from registers (positions match)
+            // the last forward pass's placement is the first inverse pass's
+            EI::run(y, lds, c, ES, t, tws);
+            if (primary) {
+                cx<float> *dst = a.acc + (int64_t)b * a.acc_stride;
+                if (col_ok)
 #pragma unroll
-        for (int i = 0; i < BPT; ++i) {
-            const int bb = t + i * TPL;
-            if (PI::EVEN || bb < PI::NB) dft<RL, false>(v[i]);
+                    for (int e = 0; e < E; ++e)
+                        dst[(uint32_t)(cbase + (int64_t)EI::out_pos(t, e) * s.row_stride)] = y[e];
+            } else {
+                cx<float> *dst = a.part + (int64_t)b * a.part_stride + (int64_t)w * (L * CPW) + c;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
+            }
         }
-        PI::write(lds, c, ES, t, v);
-        __syncthreads();
-        run_passes<float, L, false, 1, NP>(lds, c, ES, t, true, tw);
-        tile_store<float, L, CPW, NT, PAD>(a.acc + (int64_t)b * a.acc_stride, lds, s, col0);
-        __syncthreads();
     }
 }
 
+// tab[t] = the workgroup holding the second part of tile t, or -1
+__global__ __launch_bounds__(256) void fused_split_kernel(int *__restrict__ tab, int64_t tiles, int64_t kmax,
+                                                          int64_t P, int64_t W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    const int64_t lo = t * kmax;
+    const int64_t wc = ((lo + 1) * P + W - 1) / W;      // first workgroup starting after lo
+    int v = -1;
+    if (wc < P) {
+        const int64_t st = wc * W / P;
+        if (st > lo && st < lo + kmax) v = (int)wc;
+    }
+    tab[t] = v;
+}
+
 template <int N>
-static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
-    using SH = ColShape<float, N>;
+static void fused_sets(ColSet &s0, ColSet &s1) {
+    constexpr int CPW = FusedShape<N, Sched<N>>::CPW;
     const int64_t H = N / 2;
-    ColSet s0, s1;
     // main: columns (q, p) flat q*H + p; element (row r) at r*N*H + col
     s0.n_cols = (int64_t)N * H; s0.W = (int64_t)N * H; s0.plane_stride = 0; s0.col_stride = 1;
     s0.row_stride = (int64_t)N * H; s0.off = 0; s0.rowfast = 0;
     // nyq: columns q; element (row r) at main + r*N + q
     s1.n_cols = N; s1.W = N; s1.plane_stride = 0; s1.col_stride = 1; s1.row_stride = N;
     s1.off = spec_main(N); s1.rowfast = 0;
-    s0.n_wgs = (int32_t)((s0.n_cols + SH::CPW - 1) / SH::CPW);
-    s1.n_wgs = (int32_t)((s1.n_cols + SH::CPW - 1) / SH::CPW);
+    s0.n_wgs = (int32_t)((s0.n_cols + CPW - 1) / CPW);
+    s1.n_wgs = (int32_t)((s1.n_cols + CPW - 1) / CPW);
+}
+
+// variant 1: eight elements per thread (Sched8), where a schedule exists
+template <int N> struct HasSched8 { static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 512); };
+
+template <int N, int NB, typename S>
+static int fused_slots() {
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S>, FusedShape<N, S>::NT, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    cached = per_cu * prop.multiProcessorCount;
+    return cached;
+}
+
+template <int N, typename S>
+static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
+                               int64_t tiles, int kmax) {
+    static_assert(FusedShape<N, S>::CPW == FusedShape<N, Sched<N>>::CPW, "variants share the tiling");
+    const int slots = fa.nband == 2 ? fused_slots<N, 2, S>() : fused_slots<N, 1, S>();
+    const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts);
     FusedDev d;
     d.spec = (const cx<float> *)fa.spec; d.spec_stride = fa.spec_stride;
     d.ghat = (const float *)fa.ghat; d.oct_stride = fa.oct_stride;
     d.B = fa.B; d.band0 = fa.band0; d.K0 = fa.kcount[0]; d.K1 = fa.kcount[1];
     d.acc = (cx<float> *)fa.acc; d.acc_stride = fa.acc_stride;
+    d.part = (cx<float> *)fa.part; d.part_stride = fa.part_stride;
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
-    const int wgs = s0.n_wgs + s1.n_wgs;
+    d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
+    hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
+                       (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W);
+    constexpr int NT = FusedShape<N, S>::NT;
     if (fa.nband == 2)
-        hipLaunchKernelGGL((fused_z_kernel<N, 2>), dim3(wgs), dim3(SH::NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 2, S>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     else
-        hipLaunchKernelGGL((fused_z_kernel<N, 1>), dim3(wgs), dim3(SH::NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 1, S>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     return hipGetLastError();
 }
+
+template <int N>
+static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
+    ColSet s0, s1;
+    fused_sets<N>(s0, s1);
+    const int64_t tiles = s0.n_wgs + s1.n_wgs;
+    const int kmax = std::max(fa.kcount[0], fa.nband > 1 ? fa.kcount[1] : 0);
+    if (kmax <= 0) {
+        // no slice contributes: the accumulators are zero
+        for (int b = 0; b < fa.nband; ++b) {
+            hipError_t e = launch_fill_bytes((char *)fa.acc + (size_t)b * fa.acc_stride * 8,
+                                             fa.acc_stride * 8, st);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
+                           (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, (int64_t)tiles);
+        return hipGetLastError();
+    }
+    if constexpr (HasSched8<N>::value) {
+        if (fa.variant == 1) return fused_launch<N, Sched8<N>>(fa, tw, st, s0, s1, tiles, kmax);
+    }
+    return fused_launch<N, Sched<N>>(fa, tw, st, s0, s1, tiles, kmax);
+}
+
+int fused_variants(int n) { return (n == 64 || n == 128 || n == 256 || n == 512) ? 2 : 1; }
 
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st) {
     if (a.nband < 1 || a.nband > 2) return hipErrorInvalidValue;
@@ -227,37 +331,59 @@ hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStr
     }
 }
 
+int64_t fused_tiles(int n) {
+    switch (n) {
+#define X_(N) case N: { ColSet s0, s1; fused_sets<N>(s0, s1); return (int64_t)s0.n_wgs + s1.n_wgs; }
+        X_(8) X_(12) X_(16) X_(24) X_(32) X_(48) X_(64) X_(96) X_(128) X_(192) X_(256) X_(384) X_(512)
+#undef X_
+        default: return 0;
+    }
+}
+
+int fused_cpw(int n) {
+    switch (n) {
+#define X_(N) case N: return FusedShape<N, Sched<N>>::CPW;
+        X_(8) X_(12) X_(16) X_(24) X_(32) X_(48) X_(64) X_(96) X_(128) X_(192) X_(256) X_(384) X_(512)
+#undef X_
+        default: return 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 mean (DC) of each band: mu_b = sum_k G^_{k,b}(0) S^_k(0) / N^3
+// Stage 1: one workgroup per slice sums that slice's per-workgroup FP64
+// partials of the forward x pass (fixed order: deterministic).
+// Stage 2: one workgroup forms mu_b from the slice sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void dc_reduce_kernel(const double *__restrict__ dcpart, int K, int W,
-                                                        const double *__restrict__ g0, int B,
-                                                        double inv_n3, double *__restrict__ mu) {
+__global__ __launch_bounds__(256) void dc_slice_kernel(const double *__restrict__ dcpart, int W,
+                                                       double *__restrict__ sk) {
     __shared__ double red[256];
-    __shared__ double sk[1024];
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int w = threadIdx.x; w < W; w += 256) s += dcpart[(int64_t)k * W + w];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) sk[k] = red[0];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < W; w += 256) s += dcpart[(int64_t)k * W + w];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if ((int)threadIdx.x < B) {
+    if (threadIdx.x == 0) sk[k] = red[0];
+}
+
+__global__ __launch_bounds__(64) void dc_mu_kernel(const double *__restrict__ sk, int K,
+                                                   const double *__restrict__ g0, int B, double inv_n3,
+                                                   double *__restrict__ mu) {
+    for (int b = threadIdx.x; b < B; b += 64) {
         double m = 0.0;
-        for (int k = 0; k < K; ++k) m += g0[(int64_t)k * B + threadIdx.x] * sk[k];
-        mu[threadIdx.x] = m * inv_n3;
+        for (int k = 0; k < K; ++k) m += g0[(int64_t)k * B + b] * sk[k];
+        mu[b] = m * inv_n3;
     }
 }
 
 hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
-                            double inv_n3, double *mu, hipStream_t st) {
-    if (K > 1024 || B > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(dc_reduce_kernel, dim3(1), dim3(256), 0, st, dcpart, K, W, g0, B, inv_n3, mu);
+                            double inv_n3, double *sk, double *mu, hipStream_t st) {
+    hipLaunchKernelGGL(dc_slice_kernel, dim3(K), dim3(256), 0, st, dcpart, W, sk);
+    hipLaunchKernelGGL(dc_mu_kernel, dim3(1), dim3(64), 0, st, sk, K, g0, B, inv_n3, mu);
     return hipGetLastError();
 }
 

@@ -118,11 +118,21 @@ __global__ __launch_bounds__(256) void greens_fold_kernel(const cx<double> *__re
         mre = fmax(mre, fabs(v.x));
         if (e == 0) *dc = v.x * f;
     }
+    __shared__ double red[2][4];
     for (int o = 32; o > 0; o >>= 1) {
         mim = fmax(mim, __shfl_down(mim, o, 64));
         mre = fmax(mre, __shfl_down(mre, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = mim;
+        red[1][threadIdx.x >> 6] = mre;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) {
+            mim = fmax(mim, red[0][w]);
+            mre = fmax(mre, red[1][w]);
+        }
         // non-negative doubles order like their bit patterns
         atomicMax(&maxima[0], (unsigned long long)__double_as_longlong(mim));
         atomicMax(&maxima[1], (unsigned long long)__double_as_longlong(mre));
@@ -134,7 +144,7 @@ hipError_t launch_greens_fold(int n, const void *spec64, void *oct, bool oct_f64
                               hipStream_t st) {
     const int64_t HP = n / 2 + 1;
     const int64_t total = HP * HP * HP;
-    const int wgs = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    const int wgs = (int)std::min<int64_t>((total + 255) / 256, 1024);
     if (oct_f64)
         hipLaunchKernelGGL(greens_fold_kernel<double>, dim3(wgs), dim3(256), 0, st,
                            (const cx<double> *)spec64, (double *)oct, n, conserve, target_over_l3, dc,

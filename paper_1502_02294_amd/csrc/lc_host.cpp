@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -52,6 +53,8 @@ int ok() {
     } while (0)
 
 constexpr size_t kAlign = 256;
+// persistent workgroups of the fused pass can never exceed this (256 CUs x 8)
+constexpr int64_t kMaxParts = 2048;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // ---- special functions (host, FP64) ---------------------------------------
@@ -218,7 +221,11 @@ struct BoxPlan {
     std::vector<uint8_t> pushed;
     // device regions
     char *spec = nullptr, *acc = nullptr, *ghat = nullptr;
-    double *ghat0 = nullptr, *dcpart = nullptr, *mu = nullptr;
+    double *ghat0 = nullptr, *dcpart = nullptr, *mu = nullptr, *sk = nullptr;
+    char *part = nullptr;        // FP32 form: second parts of split fused tiles, 2 bands
+    int *split_tab = nullptr;    // per band pair slot: tile -> part slot
+    int64_t max_parts = 0, part_stride = 0, tiles = 0;
+    int fused_variant = 0;
     unsigned long long *maxima = nullptr;
     char *tw_half = nullptr, *tw_full = nullptr, *twist = nullptr;       // plan precision
     char *tw64_half = nullptr, *tw64_full = nullptr, *twist64 = nullptr; // FP64 (builder)
@@ -246,7 +253,7 @@ namespace {
 struct Layout {
     size_t total = 0;
     struct BoxOff {
-        size_t spec, acc, ghat, ghat0, dcpart, mu, maxima, tw_half, tw_full, twist, tw64_half,
+        size_t spec, acc, ghat, ghat0, dcpart, mu, sk, part, split_tab, maxima, tw_half, tw_full, twist, tw64_half,
             tw64_full, twist64;
     };
     std::vector<BoxOff> box;
@@ -313,6 +320,13 @@ Layout layout_of(const lc_plan_desc *d) {
         o.ghat0 = take((size_t)K * B * 8);
         o.dcpart = take((size_t)K * x_pass_wgs(n) * 8);
         o.mu = take((size_t)B * 8);
+        o.sk = take((size_t)K * 8);
+        if (d->precision == LC_PREC_FP32) {
+            o.part = take((size_t)2 * kMaxParts * n * fused_cpw(n) * 8);
+            o.split_tab = take((size_t)((B + 1) / 2) * fused_tiles(n) * 4);
+        } else {
+            o.part = o.split_tab = 0;
+        }
         o.maxima = take((size_t)B * 2 * 8);
         o.tw_half = take((size_t)(n / 2) * cs);
         o.tw_full = take((size_t)n * cs);
@@ -430,7 +444,19 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         bp.pushed.assign(bp.K, 0);
         bp.spec = p->ws + o.spec; bp.acc = p->ws + o.acc; bp.ghat = p->ws + o.ghat;
         bp.ghat0 = (double *)(p->ws + o.ghat0); bp.dcpart = (double *)(p->ws + o.dcpart);
-        bp.mu = (double *)(p->ws + o.mu); bp.maxima = (unsigned long long *)(p->ws + o.maxima);
+        bp.mu = (double *)(p->ws + o.mu); bp.sk = (double *)(p->ws + o.sk);
+        if (p->prec == LC_PREC_FP32) {
+            bp.part = p->ws + o.part;
+            bp.split_tab = (int *)(p->ws + o.split_tab);
+            bp.max_parts = kMaxParts;
+            bp.part_stride = kMaxParts * x.n * fused_cpw(x.n);
+            bp.tiles = fused_tiles(x.n);
+            bp.fused_variant = fused_variants(x.n) > 1 ? 1 : 0;
+            if (const char *ev = std::getenv("LC_FUSED_VARIANT")) {
+                const int v = std::atoi(ev);
+                if (v >= 0 && v < fused_variants(x.n)) bp.fused_variant = v;
+            }
+        } bp.maxima = (unsigned long long *)(p->ws + o.maxima);
         bp.tw_half = p->ws + o.tw_half; bp.tw_full = p->ws + o.tw_full; bp.twist = p->ws + o.twist;
         bp.tw64_half = p->ws + o.tw64_half; bp.tw64_full = p->ws + o.tw64_full;
         bp.twist64 = p->ws + o.twist64;
@@ -605,9 +631,10 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
     const double inv_n3 = 1.0 / ((double)n * n * n);
     hipStream_t st = p->stream;
     if (p->prec == LC_PREC_FP32) {
-        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.xwgs, bp.ghat0, bp.B, inv_n3, bp.mu, st));
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.xwgs, bp.ghat0, bp.B, inv_n3, bp.sk, bp.mu, st));
         for (int b = b0; b < b1;) {
             const int nb = std::min(2, b1 - b);
+            int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;
             FusedArgs fa;
             fa.spec = bp.spec; fa.spec_stride = se;
             fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
@@ -615,15 +642,18 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.kcount[0] = bp.kcount[b];
             fa.kcount[1] = nb > 1 ? bp.kcount[b + 1] : 0;
             fa.acc = bp.acc + (size_t)b * se * cs; fa.acc_stride = se;
-            fa.zero_dc = 1; fa.kahan = 1;
+            fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
+            fa.split_tab = tab;
+            fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
+            for (int j = 0; j < nb; ++j) {
+                char *acc = bp.acc + (size_t)(b + j) * se * cs;
+                HIPCHK(launch_col_y_inv_combine(n, acc, bp.tw_full, tab,
+                                                bp.part + (size_t)j * bp.part_stride * 8, st));
+                HIPCHK(launch_x_inv(n, false, acc, outp[b + j - b0], out_f64, bp.tw_half, bp.twist, inv_n3,
+                                    bp.mu + b + j, st));
+            }
             b += nb;
-        }
-        for (int b = b0; b < b1; ++b) {
-            char *acc = bp.acc + (size_t)b * se * cs;
-            HIPCHK(launch_col(n, false, 1, false, acc, bp.tw_full, st));
-            HIPCHK(launch_x_inv(n, false, acc, outp[b - b0], out_f64, bp.tw_half, bp.twist, inv_n3, bp.mu + b,
-                                st));
         }
     } else {
         for (int b = b0; b < b1; ++b) {
@@ -772,6 +802,69 @@ int lc_greens_dc(lc_plan_t *p, int32_t box, int32_t band, double *dc) {
     HIPCHK(hipMemcpyAsync(all.data(), bp.ghat0, all.size() * 8, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     for (int k = 0; k < bp.K; ++k) dc[k] = all[(size_t)k * bp.B + band];
+    return ok();
+}
+
+int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, double *avg_ms) {
+    if (!p || !avg_ms) return fail(LC_EINVAL, "NULL argument");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box out of range");
+    if (reps < 1) return fail(LC_EINVAL, "reps must be >= 1");
+    BoxPlan &bp = p->boxes[box];
+    for (int b = 0; b < bp.B; ++b)
+        if (!bp.built[b]) return fail(LC_ESTATE, "kernels not built");
+    const bool fused = p->prec == LC_PREC_FP32;
+    const bool plain_only = kernel == LC_KERNEL_COL_Z_FWD || kernel == LC_KERNEL_MAC || kernel == LC_KERNEL_COL_Z_INV;
+    if (kernel < 0 || kernel > LC_KERNEL_X_INV) return fail(LC_EINVAL, "unknown kernel id %d", kernel);
+    if (fused && plain_only) return fail(LC_EINVAL, "kernel %d is not part of the fused form", kernel);
+    if (!fused && kernel == LC_KERNEL_FUSED_Z) return fail(LC_EINVAL, "the fused z pass belongs to LC_PREC_FP32");
+    const int n = bp.n;
+    const int64_t n3 = (int64_t)n * n * n, se = spec_elems(n);
+    const size_t cs = p->t_f64 ? 16 : 8, rs = p->t_f64 ? 8 : 4;
+    hipStream_t st = p->stream;
+    if (kernel == LC_KERNEL_X_FWD) HIPCHK(launch_fill_bytes(p->scratch_real, n3 * (int64_t)rs, st));
+    auto one = [&]() -> hipError_t {
+        char *spec0 = bp.spec, *acc0 = bp.acc;
+        switch (kernel) {
+            case LC_KERNEL_X_FWD:
+                return launch_x_fwd(n, p->t_f64, p->scratch_real, p->t_f64, spec0, bp.tw_half, bp.twist,
+                                    fused ? bp.dcpart : nullptr, st);
+            case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, spec0, bp.tw_full, st);
+            case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, spec0, bp.tw_full, st);
+            case LC_KERNEL_FUSED_Z: {
+                FusedArgs fa;
+                fa.spec = bp.spec; fa.spec_stride = se; fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
+                fa.K = bp.K; fa.B = bp.B; fa.band0 = 0; fa.nband = std::min(2, bp.B);
+                fa.kcount[0] = bp.kcount[0]; fa.kcount[1] = bp.B > 1 ? bp.kcount[1] : 0;
+                fa.acc = bp.acc; fa.acc_stride = se; fa.zero_dc = 1; fa.kahan = 1;
+                fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
+                fa.split_tab = bp.split_tab;
+                fa.variant = bp.fused_variant;
+                return launch_fused_z(n, fa, bp.tw_full, st);
+            }
+            case LC_KERNEL_MAC:
+                return launch_mac_plain(n, p->t_f64, acc0, spec0, bp.ghat, false, st);
+            case LC_KERNEL_COL_Z_INV: return launch_col(n, p->t_f64, 2, false, acc0, bp.tw_full, st);
+            case LC_KERNEL_COL_Y_INV:
+                return fused ? launch_col_y_inv_combine(n, acc0, bp.tw_full, bp.split_tab, bp.part, st)
+                             : launch_col(n, p->t_f64, 1, false, acc0, bp.tw_full, st);
+            default:
+                return launch_x_inv(n, p->t_f64, acc0, p->scratch_real, p->t_f64, bp.tw_half, bp.twist,
+                                    1.0 / (double)n3, fused ? bp.mu : nullptr, st);
+        }
+    };
+    HIPCHK(one());   // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIPCHK(one());
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
     return ok();
 }
 

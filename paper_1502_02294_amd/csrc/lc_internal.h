@@ -57,12 +57,25 @@ struct FusedArgs {
     int32_t K, B;            // slices, total bands in ghat layout
     int32_t band0, nband;    // bands handled by this launch (nband 1 or 2)
     int32_t kcount[2];       // slices with nonzero kernel, per handled band
-    void *acc;               // band b at acc + (b - band0)*spec_stride ... see launcher
+    void *acc;               // handled band j at acc + j*acc_stride (complex elements)
     int64_t acc_stride;
+    void *part;              // second parts of split tiles: [band j][slot][N*CPW] complex
+    int64_t part_stride;     // per band, >= max_parts * N * CPW
+    int64_t max_parts;       // slots available in part (caps the persistent grid)
+    void *split_tab;         // int32 per tile: slot holding its second part, or -1
     int32_t zero_dc;         // 1: drop the (0,0,0) bin (FP64 mean added later)
     int32_t kahan;           // 1: compensated sum
+    int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
 };
+int fused_variants(int n);   // number of register schedules compiled for n
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);
+int64_t fused_tiles(int n);  // column tiles of the fused pass (main + nyq)
+int fused_cpw(int n);        // columns per tile
+
+// Inverse y pass of an accumulator whose fused z pass split some tiles: the
+// second parts (split_tab, part) are added while loading. FP32 only.
+hipError_t launch_col_y_inv_combine(int n, void *spec, const void *tw_full, const int *split_tab,
+                                    const void *part, hipStream_t st);
 
 // Shell kernel builder (FP64): G_k on the octant, mirrored into a full N^3
 // FP64 grid.
@@ -91,8 +104,8 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
 hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
                           bool lum_f64, int64_t n_cells, hipStream_t st);
-// mu[b] = sum_k g0[k*B + b] * sum_w dcpart[k*W + w] / n3, for b < B, k < K
+// sk[k] = sum_w dcpart[k*W + w];  mu[b] = sum_k g0[k*B + b] * sk[k] / n3
 hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
-                            double inv_n3, double *mu, hipStream_t st);
+                            double inv_n3, double *sk, double *mu, hipStream_t st);
 
 }  // namespace lc
