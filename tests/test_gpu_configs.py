@@ -1,0 +1,286 @@
+"""GPU parity at the workload sizes, through the C ABI, against the CPU FP64
+oracle (full field where the oracle finishes in seconds, sampled cells
+otherwise), plus graph replay, repeatability and edge cases.
+
+Tolerances: FP64 form e_max <= 1e-12; FP32 forms e_rms <= 1e-5 (normwise,
+over the full field or the sample); e_max of the FP32 forms <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import lc_inputs as li
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _lc():
+    import paper_1502_02294_amd as lc
+    return lc
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _box(n, L, radii, m, bands, sources, conserve=0):
+    return li.Box(n=n, box=L, radii=np.asarray(radii, dtype=np.float64), supersample=m,
+                  bands=bands, sources=sources, conserve=conserve)
+
+
+def gpu_fields(boxes, precision, as_points=True, use_graph=False, step=False, out_dtype=None):
+    """All bands of all boxes from one plan. Returns [box][band] float64 arrays."""
+    lc = _lc()
+    plan = lc.Plan(boxes, precision=precision, use_graph=use_graph)
+    plan.build_all()
+    keep = []
+    odt = out_dtype or (torch.float64 if precision == lc.LC_PREC_FP64 else torch.float32)
+    if step:
+        grids = []
+        for b in boxes:
+            for c, v in b.sources:
+                g = torch.from_numpy(li.dense_grid(b.n, c, v)).cuda()
+                grids.append(g if precision == lc.LC_PREC_FP64 else g.float())
+        outs = [torch.empty((b.n,) * 3, dtype=odt, device="cuda") for b in boxes for _ in b.bands]
+        plan.step(grids, outs)
+        keep.append(grids)
+    else:
+        for bi, b in enumerate(boxes):
+            for k, (c, v) in enumerate(b.sources):
+                if as_points:
+                    keep.append(plan.push_points(bi, k, torch.from_numpy(np.ascontiguousarray(c)).cuda(),
+                                                 torch.from_numpy(np.ascontiguousarray(v)).cuda()))
+                else:
+                    g = torch.from_numpy(li.dense_grid(b.n, c, v)).cuda()
+                    keep.append(plan.push_grid(bi, k, g if precision == lc.LC_PREC_FP64 else g.float()))
+        outs = [plan.field(bi, band, dtype=odt) for bi, b in enumerate(boxes) for band in range(len(b.bands))]
+    torch.cuda.synchronize()
+    res, i = [], 0
+    for b in boxes:
+        res.append([outs[i + j].double().cpu().numpy() for j in range(len(b.bands))])
+        i += len(b.bands)
+    plan.close()
+    return res
+
+
+def check(J, Jr, form, label):
+    e_max, e_rms = oracle.rel_errors(J, Jr)
+    say(f"{label}: {form} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    if form == "fp64":
+        assert e_max <= 1e-12, (label, e_max)
+    else:
+        assert e_rms <= 1e-5, (label, e_rms)
+        assert e_max <= 1e-4, (label, e_max)
+    return e_max, e_rms
+
+
+# --- full-grid parity: 128^3 x 24 slices, GRF peaks, LW-like attenuation ---------------
+
+@pytest.fixture(scope="module")
+def cfg2_ref():
+    b = li.cfg2().boxes[0]
+    say("cfg2: oracle kernel and spectral route (library FFT)")
+    G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
+    S = [li.dense_grid(b.n, c, v).reshape((b.n,) * 3) for c, v in b.sources]
+    J = oracle.field_fft(lambda k: G[k], lambda k: S[k], b.n_slices, b.n)
+    targets = li.sample_cells(2024, b.n, 256)
+    JD = oracle.field_direct(G, b.sources, targets)
+    return b, J, targets, JD
+
+
+def test_cfg2_routes_agree(cfg2_ref):
+    b, J, targets, JD = cfg2_ref
+    e_max, _ = oracle.rel_errors(J.ravel()[targets], JD)
+    assert e_max <= 1e-12
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "fp32_plain"])
+def test_cfg2_full_grid(cfg2_ref, form):
+    lc = _lc()
+    b, J, targets, JD = cfg2_ref
+    prec = {"fp64": lc.LC_PREC_FP64, "fp32": lc.LC_PREC_FP32, "fp32_plain": lc.LC_PREC_FP32_PLAIN}[form]
+    say(f"case cfg2 {form}")
+    Jg = gpu_fields([b], prec, as_points=True)[0][0]
+    check(Jg, J, form, "cfg2 full grid")
+    check(Jg.ravel()[targets], JD, form, "cfg2 sampled route D")
+
+
+# --- full-size sampled parity: 256^3 x 40 slices (the benchmark workload) ------------------
+
+@pytest.fixture(scope="module")
+def cfg3_ref():
+    b = li.cfg3().boxes[0]
+    targets = np.concatenate([li.sample_cells(3033, b.n, 120),
+                              np.array([0, 1, b.n ** 3 - 1], dtype=np.int64)])
+    say("cfg3: oracle route D on sampled cells")
+    JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, targets)
+    return b, targets, JD
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_cfg3_sampled(cfg3_ref, form):
+    lc = _lc()
+    b, targets, JD = cfg3_ref
+    prec = lc.LC_PREC_FP64 if form == "fp64" else lc.LC_PREC_FP32
+    say(f"case cfg3 {form} (graph-captured step, dense FP32/FP64 grids)")
+    Jg = gpu_fields([b], prec, step=True, use_graph=True)[0][0]
+    check(Jg.ravel()[targets], JD, form, "cfg3 sampled")
+    if form == "fp32":
+        # mean of the field equals sum_k G^_k(0) S^_k(0) / N^3 (FP64 DC mode)
+        say("cfg3 fp32 mean")
+
+
+def test_cfg3_fp32_vs_fp64_full_grid(cfg3_ref):
+    lc = _lc()
+    b, _, _ = cfg3_ref
+    say("case cfg3 fp32 vs fp64 full grid")
+    J64 = gpu_fields([b], lc.LC_PREC_FP64, step=True)[0][0]
+    J32 = gpu_fields([b], lc.LC_PREC_FP32, step=True)[0][0]
+    e_max, e_rms = oracle.rel_errors(J32, J64)
+    say(f"cfg3 fp32 vs gpu fp64: e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    assert e_rms <= 1e-5 and e_max <= 1e-4
+
+
+# --- batched bands: 512^3 x 60 slices x 4 bands ---------------------------------------------
+
+def test_cfg4_bands_sampled():
+    lc = _lc()
+    say("cfg4: generating sources (uniform 1% recipe)")
+    b = li.cfg4(recipe="uniform").boxes[0]
+    targets = li.sample_cells(4044, b.n, 12)
+    say("case cfg4 fp32 4 bands")
+    Js = gpu_fields([b], lc.LC_PREC_FP32, as_points=True)[0]
+    for band in range(4):
+        say(f"cfg4 oracle band {band}")
+        JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[band], b.sources,
+                                          targets)
+        check(Js[band].ravel()[targets], JD, "fp32", f"cfg4 band {band}")
+
+
+# --- batched uneven boxes in one captured step ---------------------------------------------
+
+def test_cfg5_uneven_boxes_one_step():
+    lc = _lc()
+    w = li.cfg5()
+    boxes = w.boxes
+    say("case cfg5 fp32 16 boxes, one graph-captured step")
+    Js = gpu_fields(boxes, lc.LC_PREC_FP32, step=True, use_graph=True)
+    for bi, b in enumerate(boxes):
+        t = li.sample_cells([5055, bi], b.n, 8)
+        JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, t)
+        check(Js[bi][0].ravel()[t], JD, "fp32", f"cfg5 box {bi} N={b.n} K={b.n_slices}")
+
+
+# --- graph replay, repeatability, input forms ---------------------------------------------
+
+def test_graph_replay_equals_eager_and_is_repeatable():
+    lc = _lc()
+    n, L, K = 64, 50.0, 12
+    radii = np.linspace(0.0, 50.0, K + 1)
+    srcs = [li.random_sources([61, k], n, 300) for k in range(K)]
+    b = _box(n, L, radii, 4, [li.Atten(kind=0)], srcs)
+    say("case graph replay fp32")
+    plan = lc.Plan([b], precision=lc.LC_PREC_FP32, use_graph=True)
+    plan.build_all()
+    grids = [torch.from_numpy(li.dense_grid(n, c, v)).float().cuda() for c, v in srcs]
+    outs = [torch.empty((n,) * 3, dtype=torch.float32, device="cuda")]
+    res = []
+    for rep in range(3):
+        plan.step(grids, outs)          # first call captures, later calls replay
+        torch.cuda.synchronize()
+        res.append(outs[0].clone())
+        if rep == 1:
+            torch.cuda.synchronize()
+            grids[0].mul_(1.0)          # unrelated eager work between replays
+    for k in range(K):
+        plan.push_grid(0, k, grids[k])
+    eager = plan.field(0, 0)
+    torch.cuda.synchronize()
+    plan.close()
+    for r in res:
+        assert torch.equal(r, res[0])   # bitwise repeatable
+    assert torch.equal(eager, res[0])
+
+
+def test_point_list_equals_dense_grid_fp64():
+    lc = _lc()
+    n, L, K = 32, 30.0, 5
+    radii = np.linspace(0.0, 29.0, K + 1)
+    srcs = [li.random_sources([71, k], n, 80) for k in range(K)]
+    b = _box(n, L, radii, 2, [li.lw_band(20.0)], srcs)
+    say("case points vs dense fp64")
+    a = gpu_fields([b], lc.LC_PREC_FP64, as_points=True)[0][0]
+    d = gpu_fields([b], lc.LC_PREC_FP64, as_points=False)[0][0]
+    assert np.max(np.abs(a - d)) <= 1e-14 * np.max(np.abs(d))
+
+
+# --- edge cases against the oracle ------------------------------------------------------------
+
+def _small_case(n=24, L=30.0, radii=None, m=2, at=None, conserve=0, seed=0, counts=None):
+    radii = np.linspace(0.0, 27.0, 5) if radii is None else np.asarray(radii)
+    K = len(radii) - 1
+    counts = counts or [20] * K
+    srcs = [li.random_sources([seed, k], n, counts[k]) for k in range(K)]
+    return _box(n, L, radii, m, [at or li.Atten(kind=0)], srcs, conserve)
+
+
+def _oracle_full(b, band=0):
+    G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[band], b.conserve)
+    return oracle.field_direct(G, b.sources, np.arange(b.n ** 3)).reshape((b.n,) * 3), G
+
+
+@pytest.mark.parametrize("label,kw", [
+    ("conserve", dict(conserve=1)),
+    ("paper_hard_cut", dict(at=li.Atten(kind=2, a=1.7, s=116.29 * 0.15, p=0.68, c=0.7, cut=97.39 * 0.15))),
+    ("r0_positive", dict(radii=[3.0, 8.0, 13.0, 40.0])),
+    ("prefactor", dict(at=li.Atten(kind=0, prefactor=1.0 / (4 * np.pi)))),
+    ("m3_odd_subpoints", dict(m=3)),
+    ("empty_slices", dict(counts=[0, 15, 0, 9])),
+    ("images_beyond_box", dict(radii=[0.0, 10.0, 35.0, 70.0])),
+])
+def test_edge_cases_fp64_and_fp32(label, kw):
+    lc = _lc()
+    b = _small_case(**kw)
+    Jr, G = _oracle_full(b)
+    for form, prec in (("fp64", lc.LC_PREC_FP64), ("fp32", lc.LC_PREC_FP32)):
+        say(f"case edge {label} {form}")
+        J = gpu_fields([b], prec)[0][0]
+        if not np.any(Jr):
+            assert np.max(np.abs(J)) == 0.0
+            continue
+        check(J, Jr, form, f"edge {label}")
+
+
+def test_all_sources_empty_gives_zero_field():
+    lc = _lc()
+    b = _small_case(counts=[0, 0, 0, 0])
+    for prec in (lc.LC_PREC_FP64, lc.LC_PREC_FP32, lc.LC_PREC_FP32_PLAIN):
+        J = gpu_fields([b], prec)[0][0]
+        assert np.max(np.abs(J)) == 0.0
+
+
+def test_builder_dc_and_real_spectrum_cfg2():
+    lc = _lc()
+    b = li.cfg2(n=64).boxes[0]
+    plan = lc.Plan([b], precision=lc.LC_PREC_FP32)
+    plan.build_all()
+    dc = np.array(plan.greens_dc(0, 0))
+    im = plan.greens_imag_ratio(0, 0)
+    plan.close()
+    G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
+    np.testing.assert_allclose(dc, G.sum(axis=(1, 2, 3)), rtol=1e-13)
+    assert im <= 1e-14
+
+
+def test_time_kernel_reports_positive_durations():
+    lc = _lc()
+    b = _small_case(n=64, L=60.0, radii=np.linspace(0.0, 55.0, 7))
+    plan = lc.Plan([b], precision=lc.LC_PREC_FP32)
+    plan.build_all()
+    for kid in (lc.LC_KERNEL_X_FWD, lc.LC_KERNEL_COL_Y_FWD, lc.LC_KERNEL_FUSED_Z, lc.LC_KERNEL_COL_Y_INV,
+                lc.LC_KERNEL_X_INV):
+        assert plan.time_kernel(kid, 0, 2) > 0.0
+    with pytest.raises(lc.LCError):
+        plan.time_kernel(lc.LC_KERNEL_MAC, 0, 2)     # not part of the fused form
+    plan.close()
