@@ -43,15 +43,15 @@ def src_hash() -> str:
 
 def workload(name):
     import lc_inputs as li
-    if name == "cfg3":
-        w = li.cfg3()
+    if name == "grid256":
+        w = li.points_256c_40s()
         desc = ("256^3 periodic grid, 200 Mpc box, 40 slices of 5 Mpc (0-200 Mpc), "
                 "uniform lognormal sources x1.15 per slice (355816 total), phi=1, m=4")
-    elif name == "cfg1":
-        w = li.cfg1()
+    elif name == "grid32":
+        w = li.points_32c_8s()
         desc = "32^3 grid, 20 Mpc box, 8 slices over 0-20 Mpc, 200 sources/slice, phi=1, m=1"
-    elif name == "cfg2":
-        w = li.cfg2()
+    elif name == "grid128":
+        w = li.grf_128c_24s()
         desc = ("128^3 grid, 100 Mpc box, 24 slices over 0-100 Mpc, top-1% GRF peaks, "
                 "LW-like attenuation s=116 Mpc, m=4")
     else:
@@ -123,7 +123,7 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
         model = bytes_model(n, K, min(B, 2) if fused else B, fused, csz, rsz)
         kern = {}
         for name, kid in ids.items():
-            reps = 3 if name == "fused_z" else 20
+            reps = 3 if name == "fused_z" else 2 * K
             t = plan.time_kernel(kid, 0, reps)
             kern[name] = {"avg_ms": t, "launches_per_step": per_step[name],
                           "alg_bytes": model[name],
@@ -162,12 +162,26 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--workload", default="grid256", choices=["grid32", "grid128", "grid256"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="skip the per-kernel timing (for profiler runs of the step alone)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                         "(reference for the profiler's byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration, "copies": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path runs on a "
               f"single MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -184,7 +198,8 @@ def main():
     host = [li.dense_grid(n, c, v) for c, v in box.sources]
     g32 = [torch.from_numpy(h.astype(np.float32)).cuda() for h in host]
     log("fp32 form: build + timed steps")
-    r32, out32 = run_form(lc, torch, box, g32, lc.LC_PREC_FP32, args.steps, args.warmup)
+    r32, out32 = run_form(lc, torch, box, g32, lc.LC_PREC_FP32, args.steps, args.warmup,
+                          time_kernels=not args.no_kernel_times)
     log(f"fp32 {r32['ms_per_step']:.3f} ms/step")
     line = {
         "metric": METRIC, "value": r32["value"], "unit": "cell-slices/s", "n_gpus": 1,
@@ -195,6 +210,9 @@ def main():
                    "form": "FP32 butterflies, Kahan slice sum, FP64 twiddles/kernels/mean",
                    "input": "dense FP32 source grids resident in HBM", "graph": True},
     }
+    if args.no_kernel_times:
+        print(json.dumps(line), flush=True)
+        return
     kern = r32["kernels"]
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches_per_step"])
     kd = kern[dom]

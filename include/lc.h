@@ -211,13 +211,16 @@ typedef enum {
 } lc_kernel_id;
 
 /* Diagnostic: launch one kernel of the path `reps` times back to back on
- * the plan's stream, on the buffers of slice 0 / band 0 of `box`, and
- * return the mean duration per launch measured with HIP events recorded on
- * that stream. Kernels are built and slices pushed beforehand; the source
- * of LC_KERNEL_X_FWD is a zeroed FP64 or FP32 grid (plan precision) in
- * the workspace scratch and the output of LC_KERNEL_X_INV goes there too.
- * Synchronises the stream. Errors: LC_EINVAL (bad id, reps < 1, kernel
- * not part of this plan's form), LC_ESTATE (kernels not built). */
+ * the plan's stream and return the mean duration per launch measured with
+ * HIP events recorded on that stream. Per-slice kernels cycle over the
+ * box's slices; LC_KERNEL_X_FWD reads the dense device grid most recently
+ * pushed for the slice (a zeroed scratch grid if none); per-band kernels
+ * use band 0 (the fused pass handles bands 0-1); the output of
+ * LC_KERNEL_X_INV goes to the workspace scratch. Kernels must be built.
+ * The plan's spectra and accumulators are left unspecified: push every
+ * slice again before the next lc_field. Synchronises the stream.
+ * Errors: LC_EINVAL (bad id, reps < 1, kernel not part of this plan's
+ * form), LC_ESTATE (kernels not built). */
 int lc_time_kernel(lc_plan_t *plan, int32_t box, int32_t kernel, int32_t reps, double *avg_ms);
 
 #ifdef __cplusplus

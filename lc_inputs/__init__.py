@@ -123,7 +123,7 @@ def lw_band(horizon: float) -> Atten:
 
 # --- the five workloads ------------------------------------------------------
 
-def cfg1(seed_base: int = 1) -> Workload:
+def points_32c_8s(seed_base: int = 1) -> Workload:
     """32^3, 20 Mpc, 8 equal slices over 0-20 Mpc, 200 uniform sources/slice,
     phi = 1, node rule (m = 1)."""
     n, L, K = 32, 20.0, 8
@@ -133,10 +133,10 @@ def cfg1(seed_base: int = 1) -> Workload:
         srcs.append(uniform_sources(rng, n ** 3, 200))
     b = Box(n=n, box=L, radii=equal_radii(20.0, K), supersample=1,
             bands=[Atten(kind=0)], sources=srcs)
-    return Workload("cfg1_32c_8s_fp64", [b])
+    return Workload("grid32_slices8", [b])
 
 
-def cfg2(seed_base: int = 2, n: int = 128) -> Workload:
+def grf_128c_24s(seed_base: int = 2, n: int = 128) -> Workload:
     """128^3, 100 Mpc, 24 slices over 0-100 Mpc, top-1% GRF peaks, LW-like
     attenuation with s = 116 Mpc, m = 4."""
     L, K = 100.0 * n / 128, 24
@@ -146,27 +146,27 @@ def cfg2(seed_base: int = 2, n: int = 128) -> Workload:
         srcs.append(grf_peak_sources(rng, n))
     b = Box(n=n, box=L, radii=equal_radii(L, K), supersample=4,
             bands=[Atten(kind=1, a=1.7, s=116.0, p=0.68, c=0.7)], sources=srcs)
-    return Workload(f"cfg2_{n}c_24s", [b])
+    return Workload(f"grid{n}_slices24_grf", [b])
 
 
-def cfg3_counts(K: int = 40) -> List[int]:
+def growing_counts(K: int = 40) -> List[int]:
     return [int(round(200 * 1.15 ** (K - 1 - k))) for k in range(K)]
 
 
-def cfg3(seed_base: int = 3, n: int = 256, K: int = 40) -> Workload:
+def points_256c_40s(seed_base: int = 3, n: int = 256, K: int = 40) -> Workload:
     """256^3, 200 Mpc, 40 slices of 5 Mpc, uniform lognormal sources whose
     count grows x1.15 per slice toward the present, phi = 1, m = 4."""
     L = 200.0 * n / 256
     srcs = []
-    for k, cnt in enumerate(cfg3_counts(K)):
+    for k, cnt in enumerate(growing_counts(K)):
         rng = np.random.default_rng([seed_base, 0, k])
         srcs.append(uniform_sources(rng, n ** 3, cnt))
     b = Box(n=n, box=L, radii=equal_radii(L, K), supersample=4,
             bands=[Atten(kind=0)], sources=srcs)
-    return Workload(f"cfg3_{n}c_{K}s", [b])
+    return Workload(f"grid{n}_slices{K}", [b])
 
 
-def cfg4(seed_base: int = 4, n: int = 512, K: int = 60,
+def bands_512c_60s(seed_base: int = 4, n: int = 512, K: int = 60,
          horizons=(100.0, 80.0, 60.0, 40.0), recipe: str = "grf") -> Workload:
     """512^3, 400 Mpc, 60 slices over 0-100 Mpc, 4 LW-like bands with
     horizons 100/80/60/40 Mpc sharing the sources."""
@@ -182,10 +182,10 @@ def cfg4(seed_base: int = 4, n: int = 512, K: int = 60,
     bands = [lw_band(h * n / 512) for h in horizons]
     b = Box(n=n, box=L, radii=equal_radii(r_max, K), supersample=4,
             bands=bands, sources=srcs)
-    return Workload(f"cfg4_{n}c_{K}s_{len(bands)}b", [b])
+    return Workload(f"grid{n}_slices{K}_bands{len(bands)}", [b])
 
 
-def cfg5(seed_base: int = 5, sizes=(64, 96, 128, 192, 256), n_boxes: int = 16,
+def uneven_16boxes(seed_base: int = 5, sizes=(64, 96, 128, 192, 256), n_boxes: int = 16,
          k_range=(8, 48), density: float = 1e-3) -> Workload:
     """16 independent boxes with N drawn from {64,96,128,192,256}, cell size
     0.78125 Mpc, 8..48 equal slices spanning the box side, Poisson sources."""
@@ -202,7 +202,7 @@ def cfg5(seed_base: int = 5, sizes=(64, 96, 128, 192, 256), n_boxes: int = 16,
             srcs.append(poisson_sources(rng, n, density))
         boxes.append(Box(n=n, box=L, radii=equal_radii(L, K), supersample=4,
                          bands=[Atten(kind=0)], sources=srcs))
-    return Workload(f"cfg5_{n_boxes}boxes", boxes)
+    return Workload(f"uneven{n_boxes}boxes", boxes)
 
 
 def random_sources(seed, n: int, count: int):

@@ -18,12 +18,19 @@ namespace lc {
 // ---------------------------------------------------------------------------
 template <typename T, typename TIN, int N, bool DC>
 __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
-    const TIN *__restrict__ in, cx<T> *__restrict__ mainp, cx<T> *__restrict__ nyq, int64_t n_rows,
-    const cx<T> *__restrict__ tw_g, const cx<T> *__restrict__ twist_g, double *__restrict__ dcpart) {
+    SrcTab srcs, cx<T> *__restrict__ spec0, int64_t spec_stride, int64_t n_rows, int wgs,
+    const cx<T> *__restrict__ tw_g, const cx<T> *__restrict__ twist_g, double *__restrict__ dcpart0) {
+    // workgroup blockIdx.x handles row block (blockIdx.x % wgs) of slice (blockIdx.x / wgs)
+    const int slice = blockIdx.x / wgs, blk = blockIdx.x % wgs;
+    const TIN *__restrict__ in = (const TIN *)srcs.p[slice];
+    cx<T> *__restrict__ mainp = spec0 + slice * spec_stride;
+    cx<T> *__restrict__ nyq = mainp + spec_main(N);
+    double *__restrict__ dcpart = dcpart0 ? dcpart0 + (int64_t)slice * wgs : nullptr;
     constexpr int L = N / 2;
     using SH = RowShape<T, L>;
-    using EN = Engine<T, L, true>;
-    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD, E = EN::E;
+    constexpr int SK = SH::SK;
+    using EN = Engine<T, L, true, Sched<L>, SK>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = SH::LS, E = EN::E;
     __shared__ cx<T> lds[RPW * LS];
     __shared__ cx<T> tws[L];
     __shared__ cx<T> twst[L];
@@ -32,7 +39,7 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
         tws[i] = tw_g[i];
         twst[i] = twist_g[i];
     }
-    const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    const int64_t row0 = (int64_t)blk * RPW;
     const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int64_t row = row0 + line;
     const bool active = row < n_rows;
@@ -42,22 +49,23 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
     for (int e = 0; e < E; ++e) {
         const int p = EN::in_pos(t, e);
         if (active) {
-            const TIN a = in[row * N + 2 * p], b = in[row * N + 2 * p + 1];
-            x[e] = mk((T)a, (T)b);
-            if (DC) dsum += (double)a + (double)b;
+            // one 2-element vector load (rows start 2-element aligned)
+            const cx<TIN> ab = *(const cx<TIN> *)(in + row * N + 2 * p);
+            x[e] = mk((T)ab.x, (T)ab.y);
+            if (DC) dsum += (double)ab.x + (double)ab.y;
         } else {
             x[e] = mk((T)0, (T)0);
         }
     }
     EN::run(x, lds, line * LS, 1, t, tws);
-    __syncthreads();
+    lds_barrier();
     cx<T> *z = lds + line * LS;
 #pragma unroll
-    for (int e = 0; e < E; ++e) z[EN::out_pos(t, e)] = x[e];
-    __syncthreads();
+    for (int e = 0; e < E; ++e) z[lpos<SK>(EN::out_pos(t, e))] = x[e];
+    lds_barrier();
     if (active) {
         for (int p = t; p <= L / 2; p += TPL) {
-            const cx<T> A = z[p], B = z[(L - p) % L];
+            const cx<T> A = z[lpos<SK>(p)], B = z[lpos<SK>((L - p) % L)];
             const cx<T> Ev = mk((A.x + B.x) * (T)0.5, (A.y - B.y) * (T)0.5);
             // O = (A - conj B) / (2i)
             const cx<T> O = mk((A.y + B.y) * (T)0.5, (B.x - A.x) * (T)0.5);
@@ -72,11 +80,11 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_fwd_kernel(
         // workgroup sum of the FP64 partials (fixed order: deterministic)
         for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dsum;
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0) {
             double s = 0.0;
             for (int w = 0; w < NT / 64; ++w) s += red[w];
-            dcpart[blockIdx.x] = s;
+            dcpart[blk] = s;
         }
     }
 }
@@ -91,8 +99,8 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_inv_kernel(
     const double *__restrict__ mu) {
     constexpr int L = N / 2;
     using SH = RowShape<T, L>;
-    using EN = Engine<T, L, false>;
-    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = L + SH::PAD, E = EN::E;
+    using EN = Engine<T, L, false, Sched<L>, SH::SK>;
+    constexpr int TPL = SH::TPL, NT = SH::NT, RPW = SH::RPW, LS = SH::LS, E = EN::E;
     __shared__ cx<T> lds[RPW * LS];
     __shared__ cx<T> tws[L];
     __shared__ cx<T> twst[L];
@@ -100,7 +108,7 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_inv_kernel(
         tws[i] = tw_g[i];
         twst[i] = twist_g[i];
     }
-    __syncthreads();
+    lds_barrier();
     const int64_t row0 = (int64_t)blockIdx.x * RPW;
     const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
     const int64_t row = row0 + line;
@@ -128,9 +136,10 @@ __global__ __launch_bounds__((RowShape<T, N / 2>::NT)) void x_inv_kernel(
         const double m = mu ? *mu : 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int64_t g = row * N + 2 * EN::out_pos(t, e);
-            out[g] = (TOUT)((double)x[e].x * scale + m);
-            out[g + 1] = (TOUT)((double)x[e].y * scale + m);
+            cx<TOUT> o;
+            o.x = (TOUT)((double)x[e].x * scale + m);
+            o.y = (TOUT)((double)x[e].y * scale + m);
+            *(cx<TOUT> *)(out + row * N + 2 * EN::out_pos(t, e)) = o;
         }
     }
 }
@@ -152,17 +161,21 @@ __device__ __forceinline__ void col_lane(bool rowfast, int &c, int &t) {
 
 template <typename T, int L, bool FWD, bool COMBINE>
 __global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(
-    cx<T> *data, ColSet s0, ColSet s1, const cx<T> *__restrict__ tw_g, const int *__restrict__ tab,
-    const cx<T> *__restrict__ part, int64_t tiles_main, int cpw_z) {
+    cx<T> *data0, int64_t data_stride, ColSet s0, ColSet s1, const cx<T> *__restrict__ tw_g,
+    const int *__restrict__ tab, const cx<T> *__restrict__ part, int64_t tiles_main, int cpw_z) {
+    // workgroup blockIdx.x handles tile (blockIdx.x % per) of spectrum (blockIdx.x / per)
+    const int per = s0.n_wgs + s1.n_wgs;
+    const int bid = blockIdx.x % per;
+    cx<T> *data = data0 + (int64_t)(blockIdx.x / per) * data_stride;
     using SH = ColShape<T, L>;
     using EN = Engine<T, L, FWD>;
     constexpr int CPW = SH::CPW, NT = SH::NT, ES = CPW + SH::PAD, E = EN::E, TPL = SH::TPL;
     __shared__ cx<T> lds[L * ES];
     __shared__ cx<T> tws[L];
     for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
-    const bool first = (int)blockIdx.x < s0.n_wgs;
+    const bool first = bid < s0.n_wgs;
     const ColSet &s = first ? s0 : s1;
-    const int64_t col0 = (int64_t)(first ? blockIdx.x : blockIdx.x - s0.n_wgs) * CPW;
+    const int64_t col0 = (int64_t)(first ? bid : bid - s0.n_wgs) * CPW;
     int c, t;
     col_lane<CPW, TPL>(s.rowfast, c, t);
     const int64_t col = col0 + c;
@@ -235,34 +248,41 @@ int x_pass_wgs(int n) {
 }
 
 template <typename T, typename TIN, int N>
-static hipError_t x_fwd_t(const void *in, void *spec, const void *tw, const void *twist,
-                          double *dcpart, hipStream_t st) {
+static hipError_t x_fwd_t(const SrcTab &in, int count, void *spec, int64_t spec_stride, const void *tw,
+                          const void *twist, double *dcpart, hipStream_t st) {
     using SH = RowShape<T, N / 2>;
     static_assert(SH::RPW == RowShape<float, N / 2>::RPW, "rows per WG must not depend on T");
     const int64_t rows = (int64_t)N * N;
     const int wgs = (int)((rows + SH::RPW - 1) / SH::RPW);
-    cx<T> *sp = (cx<T> *)spec;
+    const dim3 grid((unsigned)(wgs * count));
     if (dcpart)
-        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, true>), dim3(wgs), dim3(SH::NT), 0, st,
-                           (const TIN *)in, sp, sp + spec_main(N), rows, (const cx<T> *)tw,
-                           (const cx<T> *)twist, dcpart);
+        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, true>), grid, dim3(SH::NT), 0, st, in, (cx<T> *)spec,
+                           spec_stride, rows, wgs, (const cx<T> *)tw, (const cx<T> *)twist, dcpart);
     else
-        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, false>), dim3(wgs), dim3(SH::NT), 0, st,
-                           (const TIN *)in, sp, sp + spec_main(N), rows, (const cx<T> *)tw,
-                           (const cx<T> *)twist, dcpart);
+        hipLaunchKernelGGL((x_fwd_kernel<T, TIN, N, false>), grid, dim3(SH::NT), 0, st, in, (cx<T> *)spec,
+                           spec_stride, rows, wgs, (const cx<T> *)tw, (const cx<T> *)twist, dcpart);
     return hipGetLastError();
+}
+
+hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bool in_f64, void *spec,
+                              int64_t spec_stride, const void *tw_half, const void *twist, double *dcpart,
+                              hipStream_t st) {
+    if (count < 1 || count > SrcTab::kMax) return hipErrorInvalidValue;
+#define X_(N)                                                                                          \
+    if (t_f64) return in_f64 ? x_fwd_t<double, double, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st) \
+                             : x_fwd_t<double, float, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st); \
+    else return in_f64 ? x_fwd_t<float, double, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st)       \
+                       : x_fwd_t<float, float, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st);
+    LC_DISPATCH_N(n, X_)
+#undef X_
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_x_fwd(int n, bool t_f64, const void *in, bool in_f64, void *spec,
                         const void *tw_half, const void *twist, double *dcpart, hipStream_t st) {
-#define X_(N)                                                                                \
-    if (t_f64) return in_f64 ? x_fwd_t<double, double, N>(in, spec, tw_half, twist, dcpart, st) \
-                             : x_fwd_t<double, float, N>(in, spec, tw_half, twist, dcpart, st); \
-    else return in_f64 ? x_fwd_t<float, double, N>(in, spec, tw_half, twist, dcpart, st)       \
-                       : x_fwd_t<float, float, N>(in, spec, tw_half, twist, dcpart, st);
-    LC_DISPATCH_N(n, X_)
-#undef X_
-    return hipErrorInvalidValue;
+    SrcTab tab;
+    tab.p[0] = in;
+    return launch_x_fwd_batch(n, t_f64, tab, 1, in_f64, spec, 0, tw_half, twist, dcpart, st);
 }
 
 template <typename T, typename TOUT, int N>
@@ -317,16 +337,17 @@ static void col_sets(int axis, ColSet &s0, ColSet &s1) {
 }
 
 template <typename T, int N>
-static hipError_t col_t(int axis, bool fwd, void *spec, const void *tw, hipStream_t st) {
+static hipError_t col_t(int axis, bool fwd, void *spec, int64_t stride, int count, const void *tw,
+                        hipStream_t st) {
     using SH = ColShape<T, N>;
     ColSet s0, s1;
     col_sets<T, N>(axis, s0, s1);
-    const int wgs = s0.n_wgs + s1.n_wgs;
+    const dim3 grid((unsigned)((s0.n_wgs + s1.n_wgs) * count));
     if (fwd)
-        hipLaunchKernelGGL((col_kernel<T, N, true, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec,
+        hipLaunchKernelGGL((col_kernel<T, N, true, false>), grid, dim3(SH::NT), 0, st, (cx<T> *)spec, stride,
                            s0, s1, (const cx<T> *)tw, nullptr, nullptr, (int64_t)0, 1);
     else
-        hipLaunchKernelGGL((col_kernel<T, N, false, false>), dim3(wgs), dim3(SH::NT), 0, st, (cx<T> *)spec,
+        hipLaunchKernelGGL((col_kernel<T, N, false, false>), grid, dim3(SH::NT), 0, st, (cx<T> *)spec, stride,
                            s0, s1, (const cx<T> *)tw, nullptr, nullptr, (int64_t)0, 1);
     return hipGetLastError();
 }
@@ -340,8 +361,8 @@ static hipError_t col_comb_t(void *spec, const void *tw, const int *tab, const v
     const int cpw_z = SH::CPW;
     const int64_t tiles_main = ((int64_t)N * (N / 2) + cpw_z - 1) / cpw_z;
     hipLaunchKernelGGL((col_kernel<float, N, false, true>), dim3(s0.n_wgs + s1.n_wgs), dim3(SH::NT), 0, st,
-                       (cx<float> *)spec, s0, s1, (const cx<float> *)tw, tab, (const cx<float> *)part,
-                       tiles_main, cpw_z);
+                       (cx<float> *)spec, (int64_t)0, s0, s1, (const cx<float> *)tw, tab,
+                       (const cx<float> *)part, tiles_main, cpw_z);
     return hipGetLastError();
 }
 
@@ -353,14 +374,20 @@ hipError_t launch_col_y_inv_combine(int n, void *spec, const void *tw_full, cons
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,
-                      hipStream_t st) {
-#define X_(N)                                                   \
-    if (t_f64) return col_t<double, N>(axis, fwd, spec, tw_full, st); \
-    else return col_t<float, N>(axis, fwd, spec, tw_full, st);
+hipError_t launch_col_batch(int n, bool t_f64, int axis, bool fwd, void *spec, int64_t stride, int count,
+                            const void *tw_full, hipStream_t st) {
+    if (count < 1) return hipErrorInvalidValue;
+#define X_(N)                                                                        \
+    if (t_f64) return col_t<double, N>(axis, fwd, spec, stride, count, tw_full, st); \
+    else return col_t<float, N>(axis, fwd, spec, stride, count, tw_full, st);
     LC_DISPATCH_N(n, X_)
 #undef X_
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,
+                      hipStream_t st) {
+    return launch_col_batch(n, t_f64, axis, fwd, spec, 0, 1, tw_full, st);
 }
 
 }  // namespace lc

@@ -15,6 +15,18 @@
 
 namespace lc {
 
+// Workgroup barrier ordering LDS accesses only. __syncthreads() is a
+// workgroup-scope release/acquire on all memory, which on this chip family
+// waits for every outstanding global load too (one counter tracks them),
+// so prefetches issued before a barrier would be drained by it. The
+// kernels here share data between threads through LDS only; global data a
+// thread loads is consumed by that thread before its next barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
     T x, y;
@@ -197,7 +209,12 @@ template <int L, bool FWD, typename S = Sched<L>> __device__ __host__ constexpr 
 // ---- one Stockham pass ----------------------------------------------------------
 // Line elements live in LDS at lds[lbase + i*es]; thread t in [0, TPL).
 
-template <typename T, int L, int R, int NS, int TPL, bool FWD>
+// LDS position of line element p with a skew of one pad slot every 2^SK
+// elements (SK = 31: no skew). Line passes whose lines are contiguous in LDS
+// use it to spread power-of-two strides over the banks.
+template <int SK> __device__ __forceinline__ int lpos(int p) { return p + (p >> SK); }
+
+template <typename T, int L, int R, int NS, int TPL, bool FWD, int SK = 31>
 struct Pass {
     static constexpr int NB = L / R;
     static constexpr int BPT = (NB + TPL - 1) / TPL;
@@ -222,7 +239,7 @@ struct Pass {
             const int b = t + i * TPL;
             if (EVEN || b < NB) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = lds[lbase + (b + r * NB) * es];
+                for (int r = 0; r < R; ++r) v[i][r] = lds[lbase + lpos<SK>(b + r * NB) * es];
                 twiddle(v[i], b, tw);
                 dft<R, FWD>(v[i]);
             }
@@ -236,7 +253,7 @@ struct Pass {
             if (EVEN || b < NB) {
                 const int o = (b / NS) * NS * R + (b % NS);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[lbase + (o + r * NS) * es] = v[i][r];
+                for (int r = 0; r < R; ++r) lds[lbase + lpos<SK>(o + r * NS) * es] = v[i][r];
             }
         }
     }
@@ -251,26 +268,26 @@ struct Pass {
 
 // Run passes [P, PEND) of the schedule from LDS to LDS (barrier after each).
 // Every thread of the workgroup must call this.
-template <typename T, int L, bool FWD, int P, int PEND, typename S = Sched<L>>
+template <typename T, int L, bool FWD, int P, int PEND, typename S = Sched<L>, int SK = 31>
 __device__ __forceinline__ void run_passes(cx<T> *lds, int lbase, int es, int t, bool active,
                                            const cx<T> *tw) {
     if constexpr (P < PEND) {
         constexpr int R = pass_radix<L, FWD, S>(P);
         constexpr int NS = ns_before<L, FWD, S>(P);
-        using PS = Pass<T, L, R, NS, S::TPL, FWD>;
+        using PS = Pass<T, L, R, NS, S::TPL, FWD, SK>;
         cx<T> v[PS::BPT][R];
         if (active) PS::read(lds, lbase, es, t, tw, v);
-        __syncthreads();
+        lds_barrier();
         if (active) PS::write(lds, lbase, es, t, v);
-        __syncthreads();
-        run_passes<T, L, FWD, P + 1, PEND, S>(lds, lbase, es, t, active, tw);
+        lds_barrier();
+        run_passes<T, L, FWD, P + 1, PEND, S, SK>(lds, lbase, es, t, active, tw);
     }
 }
 
 // Register-in / register-out transform of one line by TPL threads.
 // x[e] (e < E) holds, on entry, the first pass's inputs at line positions
 // in_pos(t, e) and, on return, the last pass's outputs at out_pos(t, e).
-template <typename T, int L, bool FWD, typename S = Sched<L>>
+template <typename T, int L, bool FWD, typename S = Sched<L>, int SK = 31>
 struct Engine {
     static constexpr int NP = S::NP;
     static constexpr int TPL = S::TPL;
@@ -278,8 +295,8 @@ struct Engine {
     static constexpr int R0 = pass_radix<L, FWD, S>(0);
     static constexpr int RL = pass_radix<L, FWD, S>(NP - 1);
     static constexpr int NSL = ns_before<L, FWD, S>(NP - 1);
-    using P0 = Pass<T, L, R0, 1, TPL, FWD>;
-    using PLs = Pass<T, L, RL, NSL, TPL, FWD>;
+    using P0 = Pass<T, L, R0, 1, TPL, FWD, SK>;
+    using PLs = Pass<T, L, RL, NSL, TPL, FWD, SK>;
     static_assert(P0::EVEN && PLs::EVEN, "first and last passes must give every thread whole butterflies");
     static_assert(P0::BPT * R0 == E && PLs::BPT * RL == E, "element count per thread");
 
@@ -292,12 +309,12 @@ struct Engine {
 #pragma unroll
         for (int i = 0; i < P0::BPT; ++i) dft<R0, FWD>(x + i * R0);
         if constexpr (NP > 1) {
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int i = 0; i < P0::BPT; ++i) {
                 const int o = (t + i * TPL) * R0;
 #pragma unroll
-                for (int r = 0; r < R0; ++r) lds[lbase + (o + r) * es] = x[i * R0 + r];
+                for (int r = 0; r < R0; ++r) lds[lbase + lpos<SK>(o + r) * es] = x[i * R0 + r];
             }
         }
     }
@@ -308,13 +325,13 @@ struct Engine {
 #pragma unroll
             for (int e = 0; e < E; ++e) y[e] = x[e];
         } else {
-            __syncthreads();
-            run_passes<T, L, FWD, 1, NP - 1, S>(lds, lbase, es, t, true, tw);
+            lds_barrier();
+            run_passes<T, L, FWD, 1, NP - 1, S, SK>(lds, lbase, es, t, true, tw);
 #pragma unroll
             for (int i = 0; i < PLs::BPT; ++i) {
                 const int b = t + i * TPL;
 #pragma unroll
-                for (int r = 0; r < RL; ++r) y[i * RL + r] = lds[lbase + (b + r * PLs::NB) * es];
+                for (int r = 0; r < RL; ++r) y[i * RL + r] = lds[lbase + lpos<SK>(b + r * PLs::NB) * es];
                 PLs::twiddle(y + i * RL, b, tw);
                 dft<RL, FWD>(y + i * RL);
             }
@@ -419,7 +436,8 @@ template <typename T, int L> struct RowShape {
     static constexpr int TPL = Sched<L>::TPL;
     static constexpr int NT = 256;
     static constexpr int RPW = NT / TPL;
-    static constexpr int PAD = (sizeof(T) == 4) ? 8 : 4;
+    static constexpr int SK = 4;                          // one pad slot every 16 elements
+    static constexpr int LS = L + (L >> 4) + 1;           // line stride in LDS (odd)
 };
 
 }  // namespace lc

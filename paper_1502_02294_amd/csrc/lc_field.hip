@@ -85,9 +85,11 @@ struct FusedDev {
     int32_t zero_dc, kahan;
     int32_t kmax, P;
     int64_t W;
+    int32_t rounds;            // 1: whole tiles w, w+P, ... (no split tiles)
+    int64_t tiles;
 };
 
-template <int L, int NB_, typename S>
+template <int L, int NB_, typename S, int PF>
 __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
                                                                         const cx<float> *__restrict__ tw_g) {
     using SH = FusedShape<L, S>;
@@ -95,22 +97,26 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     using EI = Engine<float, L, false, S>;    // inverse z transform
     constexpr int CPW = SH::CPW, NT = SH::NT, ES = CPW + SH::PAD, E = EF::E;
     static_assert(EI::E == E, "forward and inverse hold the same elements");
+    constexpr int HP = L / 2 + 1;
+    constexpr int RSTEP = NT / CPW;                        // = threads per column
+    constexpr int GROWS = (HP + RSTEP - 1) / RSTEP;        // octant rows loaded per thread
     __shared__ cx<float> lds[L * ES];
     __shared__ cx<float> tws[L];
+    // kernel octant rows of the tile (all folded z frequencies), double
+    // buffered by slice: rows r and L-r of a column share one entry
+    __shared__ float gl[2][NB_][HP * CPW];
     for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
 
     const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
-    const int H = L / 2, HP = H + 1;
+    const int H = L / 2;
     const int w = blockIdx.x;
     int64_t pos = (int64_t)w * a.W / a.P;
     const int64_t end = (int64_t)(w + 1) * a.W / a.P;
 
-    while (pos < end) {
-        const int64_t tile = pos / a.kmax;
-        const int k0 = (int)(pos % a.kmax);
-        const int k1 = (int)std::min<int64_t>(a.kmax, k0 + (end - pos));
-        pos += k1 - k0;
+    auto segment = [&](const int64_t tile, const int k0, const int k1) {
 
+        // readers of the LDS buffers in the previous segment are done
+        lds_barrier();
         const bool is_main = tile < s0.n_wgs;
         const ColSet &s = is_main ? s0 : s1;
         const int64_t col0 = (is_main ? tile : tile - s0.n_wgs) * CPW;
@@ -139,25 +145,38 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
             for (int e = 0; e < E; ++e) { sum[b][e] = mk(0.f, 0.f); cmp[b][e] = mk(0.f, 0.f); }
 
         // byte offsets of this thread's inputs within one slice spectrum and
-        // of its kernel values within one octant, off workgroup-uniform bases
-        // (a slice spectrum is below 4 GiB)
-        uint32_t xoff[E], goff[E];
+        // of the kernel octant rows it loads (rows t + j*RSTEP of its column),
+        // off workgroup-uniform bases (a slice spectrum is below 4 GiB)
+        uint32_t xoff[E], goff[GROWS];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e < E; ++e)
             xoff[e] = (uint32_t)((cbase + (int64_t)EF::in_pos(t, e) * s.row_stride) * 8);
-            goff[e] = (uint32_t)((gbase + fold(EF::out_pos(t, e), L) * grow) * 4);
-        }
-        // first-pass inputs of slice k0
-        cx<float> x[E];
-        {
-            const char *src = (const char *)(a.spec + (int64_t)k0 * a.spec_stride);
 #pragma unroll
-            for (int e = 0; e < E; ++e) x[e] = *(const cx<float> *)(src + xoff[e]);
+        for (int j = 0; j < GROWS; ++j) {
+            const int rf = t + j * RSTEP;
+            goff[j] = (uint32_t)((gbase + (rf < HP ? rf : 0) * grow) * 4);
         }
-        for (int k = k0; k < k1; ++k) {
-            // kernel values of this slice, issued before the next prefetch; a
-            // band without a kernel for slice k reads a valid octant, weight 0
-            float g[NB_][E];
+        // LDS slot of each output element's kernel value (folded row)
+        int gslot[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) gslot[e] = fold(EF::out_pos(t, e), L) * CPW + c;
+
+        // first-pass inputs of the next PF slices, kept in flight in a ring of
+        // register buffers (PF slices of HBM latency hidden behind compute)
+        cx<float> xb[PF][E];
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            if (k0 + j < k1) {
+                const char *src = (const char *)(a.spec + (int64_t)(k0 + j) * a.spec_stride);
+#pragma unroll
+                for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
+            }
+        }
+        // kernel octant rows of slice k are loaded one slice ahead into
+        // registers and stored to LDS during slice k; a band without a kernel
+        // for slice k reads a valid octant with weight 0
+        float gn[NB_][GROWS];
+        auto load_g = [&](int k) {
 #pragma unroll
             for (int b = 0; b < NB_; ++b) {
                 const int kc = b == 0 ? a.K0 : a.K1;
@@ -165,34 +184,54 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 const float wgt = k < kc ? 1.f : 0.f;
                 const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
 #pragma unroll
-                for (int e = 0; e < E; ++e) g[b][e] = wgt * *(const float *)(gp + goff[e]);
+                for (int j = 0; j < GROWS; ++j) gn[b][j] = wgt * *(const float *)(gp + goff[j]);
             }
-            EF::first(x, lds, c, ES, t);
-            cx<float> v[E];
-            if constexpr (EF::NP == 1) {
+        };
+        load_g(k0);
+        for (int kk = k0; kk < k1; kk += PF) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) v[e] = x[e];
-            }
-            // x is free now: prefetch the next slice while the passes run
-            if (k + 1 < k1) {
-                const char *src = (const char *)(a.spec + (int64_t)(k + 1) * a.spec_stride);
+            for (int j = 0; j < PF; ++j) {
+                const int k = kk + j;
+                if (k >= k1) break;   // uniform across the workgroup
+                // the LDS buffer k&1 was last read during slice k-2, before the
+                // barriers of slice k-1
+                float *glk = &gl[k & 1][0][0];
 #pragma unroll
-                for (int e = 0; e < E; ++e) x[e] = *(const cx<float> *)(src + xoff[e]);
-            }
-            if constexpr (EF::NP > 1) EF::rest(x, v, lds, c, ES, t, tws);
-            // compensated (Kahan) sum over slices
+                for (int b = 0; b < NB_; ++b)
 #pragma unroll
-            for (int b = 0; b < NB_; ++b)
+                    for (int jj = 0; jj < GROWS; ++jj) {
+                        const int rf = t + jj * RSTEP;
+                        if (rf < HP) glk[b * HP * CPW + rf * CPW + c] = gn[b][jj];
+                    }
+                if (k + 1 < k1) load_g(k + 1);
+                EF::first(xb[j], lds, c, ES, t);
+                cx<float> v[E];
+                if constexpr (EF::NP == 1) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const float gv = g[b][e];
-                    const float yx = gv * v[e].x - cmp[b][e].x, yy = gv * v[e].y - cmp[b][e].y;
-                    const float tx = sum[b][e].x + yx, ty = sum[b][e].y + yy;
-                    cmp[b][e].x = (tx - sum[b][e].x) - yx;
-                    cmp[b][e].y = (ty - sum[b][e].y) - yy;
-                    sum[b][e].x = tx;
-                    sum[b][e].y = ty;
+                    for (int e = 0; e < E; ++e) v[e] = xb[j][e];
+                    lds_barrier();    // kernel values in LDS visible
                 }
+                // buffer j is free: refill it with slice k + PF
+                if (k + PF < k1) {
+                    const char *src = (const char *)(a.spec + (int64_t)(k + PF) * a.spec_stride);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
+                }
+                if constexpr (EF::NP > 1) EF::rest(xb[j], v, lds, c, ES, t, tws);
+                // compensated (Kahan) sum over slices
+#pragma unroll
+                for (int b = 0; b < NB_; ++b)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const float gv = glk[b * HP * CPW + gslot[e]];
+                        const float yx = gv * v[e].x - cmp[b][e].x, yy = gv * v[e].y - cmp[b][e].y;
+                        const float tx = sum[b][e].x + yx, ty = sum[b][e].y + yy;
+                        cmp[b][e].x = (tx - sum[b][e].x) - yx;
+                        cmp[b][e].y = (ty - sum[b][e].y) - yy;
+                        sum[b][e].x = tx;
+                        sum[b][e].y = ty;
+                    }
+            }
         }
 
         // the (0,0,0) bin: row 0 of main column 0
@@ -219,6 +258,18 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 #pragma unroll
                 for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
             }
+        }
+        };
+    if (a.rounds) {
+        // whole tiles in rounds: all workgroups sweep the slices together
+        for (int64_t tile = w; tile < a.tiles; tile += a.P) segment(tile, 0, a.kmax);
+    } else {
+        while (pos < end) {
+            const int64_t tile = pos / a.kmax;
+            const int k0 = (int)(pos % a.kmax);
+            const int k1 = (int)std::min<int64_t>(a.kmax, k0 + (end - pos));
+            pos += k1 - k0;
+            segment(tile, k0, k1);
         }
     }
 }
@@ -255,14 +306,14 @@ static void fused_sets(ColSet &s0, ColSet &s1) {
 // variant 1: eight elements per thread (Sched8), where a schedule exists
 template <int N> struct HasSched8 { static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 512); };
 
-template <int N, int NB, typename S>
+template <int N, int NB, typename S, int PF>
 static int fused_slots() {
     static int cached = 0;
     if (cached) return cached;
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S>, FusedShape<N, S>::NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S, PF>, FusedShape<N, S>::NT, 0) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -270,11 +321,11 @@ static int fused_slots() {
     return cached;
 }
 
-template <int N, typename S>
+template <int N, typename S, int PF>
 static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                                int64_t tiles, int kmax) {
     static_assert(FusedShape<N, S>::CPW == FusedShape<N, Sched<N>>::CPW, "variants share the tiling");
-    const int slots = fa.nband == 2 ? fused_slots<N, 2, S>() : fused_slots<N, 1, S>();
+    const int slots = fa.nband == 2 ? fused_slots<N, 2, S, PF>() : fused_slots<N, 1, S, PF>();
     const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts);
     FusedDev d;
     d.spec = (const cx<float> *)fa.spec; d.spec_stride = fa.spec_stride;
@@ -284,14 +335,19 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
     d.part = (cx<float> *)fa.part; d.part_stride = fa.part_stride;
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
     d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
-    hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
-                       (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W);
+    d.rounds = fa.rounds; d.tiles = tiles;
+    if (fa.rounds)   // no tile is split: every entry -1
+        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
+                           (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, tiles);
+    else
+        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
+                           (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W);
     constexpr int NT = FusedShape<N, S>::NT;
     if (fa.nband == 2)
-        hipLaunchKernelGGL((fused_z_kernel<N, 2, S>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     else
-        hipLaunchKernelGGL((fused_z_kernel<N, 1, S>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 1, S, PF>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     return hipGetLastError();
 }
@@ -313,13 +369,20 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
                            (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, (int64_t)tiles);
         return hipGetLastError();
     }
+    // variant = 2 * schedule + (prefetch depth - 2); schedule 1 = Sched8
+    const int sched = fa.variant / 2, pf = 2 + fa.variant % 2;
     if constexpr (HasSched8<N>::value) {
-        if (fa.variant == 1) return fused_launch<N, Sched8<N>>(fa, tw, st, s0, s1, tiles, kmax);
+        if (sched == 1)
+            return pf == 3 ? fused_launch<N, Sched8<N>, 3>(fa, tw, st, s0, s1, tiles, kmax)
+                           : fused_launch<N, Sched8<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
     }
-    return fused_launch<N, Sched<N>>(fa, tw, st, s0, s1, tiles, kmax);
+    return pf == 3 ? fused_launch<N, Sched<N>, 3>(fa, tw, st, s0, s1, tiles, kmax)
+                   : fused_launch<N, Sched<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
 }
 
-int fused_variants(int n) { return (n == 64 || n == 128 || n == 256 || n == 512) ? 2 : 1; }
+// variants: bit 0 selects a prefetch depth of 3 (else 2) slices, bit 1 the
+// eight-element schedule where one exists
+int fused_variants(int n) { return (n == 64 || n == 128 || n == 256 || n == 512) ? 4 : 2; }
 
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st) {
     if (a.nband < 1 || a.nband > 2) return hipErrorInvalidValue;

@@ -219,13 +219,16 @@ struct BoxPlan {
     std::vector<double> radii, T;
     std::vector<int> built, kcount;
     std::vector<uint8_t> pushed;
+    // dense device sources of the most recent push of each slice (diagnostic timing)
+    std::vector<const void *> last_src;
+    std::vector<uint8_t> last_src_f64;
     // device regions
     char *spec = nullptr, *acc = nullptr, *ghat = nullptr;
     double *ghat0 = nullptr, *dcpart = nullptr, *mu = nullptr, *sk = nullptr;
     char *part = nullptr;        // FP32 form: second parts of split fused tiles, 2 bands
     int *split_tab = nullptr;    // per band pair slot: tile -> part slot
     int64_t max_parts = 0, part_stride = 0, tiles = 0;
-    int fused_variant = 0;
+    int fused_variant = 0, fused_rounds = 1;
     unsigned long long *maxima = nullptr;
     char *tw_half = nullptr, *tw_full = nullptr, *twist = nullptr;       // plan precision
     char *tw64_half = nullptr, *tw64_full = nullptr, *twist64 = nullptr; // FP64 (builder)
@@ -239,6 +242,7 @@ struct lc_plan_s {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int use_graph = 0;
+    int push_group = 2;
     std::vector<BoxPlan> boxes;
     char *scratch_real = nullptr;    // FP64 N^3: builder grid / source staging / host-output staging
     char *scratch_spec = nullptr;    // FP64 spectrum for the builder
@@ -422,6 +426,10 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
     p->ws = (char *)d->workspace;
     p->ws_bytes = d->workspace_bytes;
     p->use_graph = d->use_graph;
+    if (const char *eg = std::getenv("LC_PUSH_GROUP")) {
+        const int g = std::atoi(eg);
+        if (g >= 1 && g <= SrcTab::kMax) p->push_group = g;
+    }
     p->scratch_real = p->ws + lay.scratch_real;
     p->scratch_spec = p->ws + lay.scratch_spec;
     const size_t cs = p->t_f64 ? 16 : 8;
@@ -442,6 +450,8 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         bp.built.assign(bp.B, 0);
         bp.kcount.assign(bp.B, bp.K);
         bp.pushed.assign(bp.K, 0);
+        bp.last_src.assign(bp.K, nullptr);
+        bp.last_src_f64.assign(bp.K, 0);
         bp.spec = p->ws + o.spec; bp.acc = p->ws + o.acc; bp.ghat = p->ws + o.ghat;
         bp.ghat0 = (double *)(p->ws + o.ghat0); bp.dcpart = (double *)(p->ws + o.dcpart);
         bp.mu = (double *)(p->ws + o.mu); bp.sk = (double *)(p->ws + o.sk);
@@ -451,7 +461,8 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             bp.max_parts = kMaxParts;
             bp.part_stride = kMaxParts * x.n * fused_cpw(x.n);
             bp.tiles = fused_tiles(x.n);
-            bp.fused_variant = fused_variants(x.n) > 1 ? 1 : 0;
+            bp.fused_variant = fused_variants(x.n) > 2 ? 2 : 0;
+            if (const char *er = std::getenv("LC_FUSED_ROUNDS")) bp.fused_rounds = std::atoi(er) ? 1 : 0;
             if (const char *ev = std::getenv("LC_FUSED_VARIANT")) {
                 const int v = std::atoi(ev);
                 if (v >= 0 && v < fused_variants(x.n)) bp.fused_variant = v;
@@ -577,9 +588,12 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
     hipStream_t st = p->stream;
     const void *in = nullptr;
     bool in_f64 = s->dtype == LC_F64;
+    bp.last_src[slice] = nullptr;
     if (s->kind == 0) {
         if (s->mem == LC_MEM_DEVICE) {
             in = s->grid;
+            bp.last_src[slice] = s->grid;
+            bp.last_src_f64[slice] = in_f64 ? 1 : 0;
         } else {
             HIPCHK(hipMemcpyAsync(p->scratch_real, s->grid, (size_t)n3 * (in_f64 ? 8 : 4),
                                   hipMemcpyHostToDevice, st));
@@ -644,7 +658,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.acc = bp.acc + (size_t)b * se * cs; fa.acc_stride = se;
             fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
             fa.split_tab = tab;
-            fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant;
+            fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
                 char *acc = bp.acc + (size_t)(b + j) * se * cs;
@@ -717,12 +731,44 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
 
 static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtype) {
     size_t si = 0, oi = 0;
+    const size_t cs = p->t_f64 ? 16 : 8;
     for (int x = 0; x < (int)p->boxes.size(); ++x) {
         BoxPlan &bp = p->boxes[x];
-        for (int k = 0; k < bp.K; ++k) {
-            int rc = push_impl(p, x, k, &srcs[si++]);
-            if (rc) return rc;
+        const int n = bp.n;
+        const int64_t se = spec_elems(n);
+        // groups of up to push_group consecutive dense slices of one value
+        // type go through one batched x pass and one batched y pass (z too
+        // for unfused forms); small groups keep each slice's spectrum in the
+        // last-level cache between its x and y passes
+        int k = 0;
+        while (k < bp.K) {
+            const lc_sources &s0 = srcs[si + k];
+            if (s0.kind != 0) {
+                int rc = push_impl(p, x, k, &s0);
+                if (rc) return rc;
+                ++k;
+                continue;
+            }
+            int cnt = 0;
+            SrcTab tab;
+            while (k + cnt < bp.K && cnt < p->push_group && srcs[si + k + cnt].kind == 0 &&
+                   srcs[si + k + cnt].dtype == s0.dtype) {
+                tab.p[cnt] = srcs[si + k + cnt].grid;
+                bp.last_src[k + cnt] = srcs[si + k + cnt].grid;
+                bp.last_src_f64[k + cnt] = s0.dtype == LC_F64 ? 1 : 0;
+                ++cnt;
+            }
+            char *spec = bp.spec + (size_t)k * se * cs;
+            double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.xwgs : nullptr;
+            HIPCHK(launch_x_fwd_batch(n, p->t_f64, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist,
+                                      dcp, p->stream));
+            HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, p->stream));
+            if (p->prec != LC_PREC_FP32)
+                HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, p->stream));
+            for (int j = 0; j < cnt; ++j) bp.pushed[k + j] = 1;
+            k += cnt;
         }
+        si += bp.K;
     }
     for (int x = 0; x < (int)p->boxes.size(); ++x) {
         BoxPlan &bp = p->boxes[x];
@@ -822,14 +868,21 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
     const size_t cs = p->t_f64 ? 16 : 8, rs = p->t_f64 ? 8 : 4;
     hipStream_t st = p->stream;
     if (kernel == LC_KERNEL_X_FWD) HIPCHK(launch_fill_bytes(p->scratch_real, n3 * (int64_t)rs, st));
+    // per-slice kernels cycle over the slices (inputs of the most recent
+    // pushes where known) so that their data stream from memory as in a step
+    int rep = 0;
     auto one = [&]() -> hipError_t {
-        char *spec0 = bp.spec, *acc0 = bp.acc;
+        const int k = rep++ % bp.K;
+        char *speck = bp.spec + (size_t)k * se * cs, *acc0 = bp.acc;
         switch (kernel) {
-            case LC_KERNEL_X_FWD:
-                return launch_x_fwd(n, p->t_f64, p->scratch_real, p->t_f64, spec0, bp.tw_half, bp.twist,
-                                    fused ? bp.dcpart : nullptr, st);
-            case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, spec0, bp.tw_full, st);
-            case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, spec0, bp.tw_full, st);
+            case LC_KERNEL_X_FWD: {
+                const void *in = bp.last_src[k] ? bp.last_src[k] : p->scratch_real;
+                const bool in_f64 = bp.last_src[k] ? bp.last_src_f64[k] != 0 : p->t_f64;
+                return launch_x_fwd(n, p->t_f64, in, in_f64, speck, bp.tw_half, bp.twist,
+                                    fused ? bp.dcpart + (size_t)k * bp.xwgs : nullptr, st);
+            }
+            case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, speck, bp.tw_full, st);
+            case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, speck, bp.tw_full, st);
             case LC_KERNEL_FUSED_Z: {
                 FusedArgs fa;
                 fa.spec = bp.spec; fa.spec_stride = se; fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
@@ -839,10 +892,12 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                 fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
                 fa.split_tab = bp.split_tab;
                 fa.variant = bp.fused_variant;
+                fa.rounds = bp.fused_rounds;
                 return launch_fused_z(n, fa, bp.tw_full, st);
             }
             case LC_KERNEL_MAC:
-                return launch_mac_plain(n, p->t_f64, acc0, spec0, bp.ghat, false, st);
+                return launch_mac_plain(n, p->t_f64, acc0, speck,
+                                        bp.ghat + (size_t)k * bp.B * oct_elems(n) * rs, false, st);
             case LC_KERNEL_COL_Z_INV: return launch_col(n, p->t_f64, 2, false, acc0, bp.tw_full, st);
             case LC_KERNEL_COL_Y_INV:
                 return fused ? launch_col_y_inv_combine(n, acc0, bp.tw_full, bp.split_tab, bp.part, st)

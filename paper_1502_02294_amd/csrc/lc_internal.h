@@ -11,8 +11,8 @@ namespace lc {
 // Spectrum of one real N^3 grid, x (contiguous) axis halved:
 //   main: [z][y][p],  p in [0, N/2)      N*N*(N/2) complex
 //   nyq : [z][y]      (p = N/2)          N*N complex
-inline int64_t spec_main(int n) { return (int64_t)n * n * (n / 2); }
-inline int64_t spec_elems(int n) { return spec_main(n) + (int64_t)n * n; }
+__host__ __device__ inline int64_t spec_main(int n) { return (int64_t)n * n * (n / 2); }
+__host__ __device__ inline int64_t spec_elems(int n) { return spec_main(n) + (int64_t)n * n; }
 // Kernel spectrum octant (real, folded |r|, |q| in [0, N/2]):
 //   main: [r][q][p], p in [0, N/2)       H*H*(N/2) reals, H = N/2+1
 //   nyq : [r][q]                         H*H reals
@@ -24,6 +24,23 @@ bool supported_n(int n);
 // Number of workgroups of the forward x pass (rows per WG depends on N);
 // the DC partial array of one slice has this many doubles.
 int x_pass_wgs(int n);
+
+// Source grid pointers of a batch of slices (passed by value as a kernel
+// argument, so no device table has to be written before a launch).
+struct SrcTab {
+    static constexpr int kMax = 64;
+    const void *p[kMax];
+};
+
+// Forward x pass of `count` slices: slice i reads in.p[i] and writes the
+// spectrum at spec + i*spec_stride (complex elements); DC partials at
+// dcpart + i*x_pass_wgs(n).
+hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bool in_f64, void *spec,
+                              int64_t spec_stride, const void *tw_half, const void *twist, double *dcpart,
+                              hipStream_t st);
+// Column pass over `count` spectra at spec + i*stride (complex elements).
+hipError_t launch_col_batch(int n, bool t_f64, int axis, bool fwd, void *spec, int64_t stride, int count,
+                            const void *tw_full, hipStream_t st);
 
 // Forward x pass: real rows -> main/nyq. in_f64 selects the input type,
 // t_f64 the working precision. dcpart (nullable) receives one FP64 partial
@@ -66,6 +83,7 @@ struct FusedArgs {
     int32_t zero_dc;         // 1: drop the (0,0,0) bin (FP64 mean added later)
     int32_t kahan;           // 1: compensated sum
     int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
+    int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
 };
 int fused_variants(int n);   // number of register schedules compiled for n
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);

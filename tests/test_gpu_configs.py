@@ -78,9 +78,9 @@ def check(J, Jr, form, label):
 # --- full-grid parity: 128^3 x 24 slices, GRF peaks, LW-like attenuation ---------------
 
 @pytest.fixture(scope="module")
-def cfg2_ref():
-    b = li.cfg2().boxes[0]
-    say("cfg2: oracle kernel and spectral route (library FFT)")
+def grid128_ref():
+    b = li.grf_128c_24s().boxes[0]
+    say("grid128: oracle kernel and spectral route (library FFT)")
     G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
     S = [li.dense_grid(b.n, c, v).reshape((b.n,) * 3) for c, v in b.sources]
     J = oracle.field_fft(lambda k: G[k], lambda k: S[k], b.n_slices, b.n)
@@ -89,87 +89,87 @@ def cfg2_ref():
     return b, J, targets, JD
 
 
-def test_cfg2_routes_agree(cfg2_ref):
-    b, J, targets, JD = cfg2_ref
+def test_grid128_routes_agree(grid128_ref):
+    b, J, targets, JD = grid128_ref
     e_max, _ = oracle.rel_errors(J.ravel()[targets], JD)
     assert e_max <= 1e-12
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32", "fp32_plain"])
-def test_cfg2_full_grid(cfg2_ref, form):
+def test_grid128_full_grid(grid128_ref, form):
     lc = _lc()
-    b, J, targets, JD = cfg2_ref
+    b, J, targets, JD = grid128_ref
     prec = {"fp64": lc.LC_PREC_FP64, "fp32": lc.LC_PREC_FP32, "fp32_plain": lc.LC_PREC_FP32_PLAIN}[form]
-    say(f"case cfg2 {form}")
+    say(f"case grid128 {form}")
     Jg = gpu_fields([b], prec, as_points=True)[0][0]
-    check(Jg, J, form, "cfg2 full grid")
-    check(Jg.ravel()[targets], JD, form, "cfg2 sampled route D")
+    check(Jg, J, form, "grid128 full grid")
+    check(Jg.ravel()[targets], JD, form, "grid128 sampled route D")
 
 
 # --- full-size sampled parity: 256^3 x 40 slices (the benchmark workload) ------------------
 
 @pytest.fixture(scope="module")
-def cfg3_ref():
-    b = li.cfg3().boxes[0]
+def grid256_ref():
+    b = li.points_256c_40s().boxes[0]
     targets = np.concatenate([li.sample_cells(3033, b.n, 120),
                               np.array([0, 1, b.n ** 3 - 1], dtype=np.int64)])
-    say("cfg3: oracle route D on sampled cells")
+    say("grid256: oracle route D on sampled cells")
     JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, targets)
     return b, targets, JD
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
-def test_cfg3_sampled(cfg3_ref, form):
+def test_grid256_sampled(grid256_ref, form):
     lc = _lc()
-    b, targets, JD = cfg3_ref
+    b, targets, JD = grid256_ref
     prec = lc.LC_PREC_FP64 if form == "fp64" else lc.LC_PREC_FP32
-    say(f"case cfg3 {form} (graph-captured step, dense FP32/FP64 grids)")
+    say(f"case grid256 {form} (graph-captured step, dense FP32/FP64 grids)")
     Jg = gpu_fields([b], prec, step=True, use_graph=True)[0][0]
-    check(Jg.ravel()[targets], JD, form, "cfg3 sampled")
+    check(Jg.ravel()[targets], JD, form, "grid256 sampled")
     if form == "fp32":
         # mean of the field equals sum_k G^_k(0) S^_k(0) / N^3 (FP64 DC mode)
-        say("cfg3 fp32 mean")
+        say("grid256 fp32 mean")
 
 
-def test_cfg3_fp32_vs_fp64_full_grid(cfg3_ref):
+def test_grid256_fp32_vs_fp64_full_grid(grid256_ref):
     lc = _lc()
-    b, _, _ = cfg3_ref
-    say("case cfg3 fp32 vs fp64 full grid")
+    b, _, _ = grid256_ref
+    say("case grid256 fp32 vs fp64 full grid")
     J64 = gpu_fields([b], lc.LC_PREC_FP64, step=True)[0][0]
     J32 = gpu_fields([b], lc.LC_PREC_FP32, step=True)[0][0]
     e_max, e_rms = oracle.rel_errors(J32, J64)
-    say(f"cfg3 fp32 vs gpu fp64: e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    say(f"grid256 fp32 vs gpu fp64: e_max={e_max:.3e} e_rms={e_rms:.3e}")
     assert e_rms <= 1e-5 and e_max <= 1e-4
 
 
 # --- batched bands: 512^3 x 60 slices x 4 bands ---------------------------------------------
 
-def test_cfg4_bands_sampled():
+def test_grid512_bands_sampled():
     lc = _lc()
-    say("cfg4: generating sources (uniform 1% recipe)")
-    b = li.cfg4(recipe="uniform").boxes[0]
+    say("grid512: generating sources (uniform 1% recipe)")
+    b = li.bands_512c_60s(recipe="uniform").boxes[0]
     targets = li.sample_cells(4044, b.n, 12)
-    say("case cfg4 fp32 4 bands")
+    say("case grid512 fp32 4 bands")
     Js = gpu_fields([b], lc.LC_PREC_FP32, as_points=True)[0]
     for band in range(4):
-        say(f"cfg4 oracle band {band}")
+        say(f"grid512 oracle band {band}")
         JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[band], b.sources,
                                           targets)
-        check(Js[band].ravel()[targets], JD, "fp32", f"cfg4 band {band}")
+        check(Js[band].ravel()[targets], JD, "fp32", f"grid512 band {band}")
 
 
 # --- batched uneven boxes in one captured step ---------------------------------------------
 
-def test_cfg5_uneven_boxes_one_step():
+def test_uneven_uneven_boxes_one_step():
     lc = _lc()
-    w = li.cfg5()
+    w = li.uneven_16boxes()
     boxes = w.boxes
-    say("case cfg5 fp32 16 boxes, one graph-captured step")
+    say("case uneven fp32 16 boxes, one graph-captured step")
     Js = gpu_fields(boxes, lc.LC_PREC_FP32, step=True, use_graph=True)
     for bi, b in enumerate(boxes):
         t = li.sample_cells([5055, bi], b.n, 8)
         JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, t)
-        check(Js[bi][0].ravel()[t], JD, "fp32", f"cfg5 box {bi} N={b.n} K={b.n_slices}")
+        check(Js[bi][0].ravel()[t], JD, "fp32", f"uneven box {bi} N={b.n} K={b.n_slices}")
 
 
 # --- graph replay, repeatability, input forms ---------------------------------------------
@@ -260,9 +260,9 @@ def test_all_sources_empty_gives_zero_field():
         assert np.max(np.abs(J)) == 0.0
 
 
-def test_builder_dc_and_real_spectrum_cfg2():
+def test_builder_dc_and_real_spectrum_grid128():
     lc = _lc()
-    b = li.cfg2(n=64).boxes[0]
+    b = li.grf_128c_24s(n=64).boxes[0]
     plan = lc.Plan([b], precision=lc.LC_PREC_FP32)
     plan.build_all()
     dc = np.array(plan.greens_dc(0, 0))

@@ -56,14 +56,14 @@ def _oracle_full(box, band=0):
     return J, G
 
 
-def test_cfg1_fp64_full_grid():
-    w = li.cfg1()
+def test_grid32_fp64_full_grid():
+    w = li.points_32c_8s()
     b = w.boxes[0]
-    print("case cfg1 fp64", flush=True)
+    print("case grid32 fp64", flush=True)
     (J,), (dc,), (im,) = _run_gpu(b, _lc().LC_PREC_FP64)
     Jr, G = _oracle_full(b)
     e_max, e_rms = oracle.rel_errors(J, Jr)
-    print(f"cfg1 fp64 e_max={e_max:.3e} e_rms={e_rms:.3e} imag={im:.2e}")
+    print(f"grid32 fp64 e_max={e_max:.3e} e_rms={e_rms:.3e} imag={im:.2e}")
     assert e_max <= 1e-12
     np.testing.assert_allclose(dc, G.sum(axis=(1, 2, 3)), rtol=1e-13)
     assert im <= 1e-14
@@ -88,16 +88,16 @@ def test_small_grids_fp64_all_schedules(n):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp32_plain"])
-def test_cfg1_fp32_forms(prec):
+def test_grid32_fp32_forms(prec):
     lc = _lc()
-    w = li.cfg1()
+    w = li.points_32c_8s()
     b = w.boxes[0]
     p = lc.LC_PREC_FP32 if prec == "fp32" else lc.LC_PREC_FP32_PLAIN
-    print(f"case cfg1 {prec}", flush=True)
+    print(f"case grid32 {prec}", flush=True)
     (J,), _, _ = _run_gpu(b, p, as_points=False)
     Jr, _ = _oracle_full(b)
     e_max, e_rms = oracle.rel_errors(J, Jr)
-    print(f"cfg1 {prec} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    print(f"grid32 {prec} e_max={e_max:.3e} e_rms={e_rms:.3e}")
     assert e_rms <= 1e-5
     assert e_max <= 1e-4
 

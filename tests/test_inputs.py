@@ -4,9 +4,9 @@ import numpy as np
 import lc_inputs as li
 
 
-def test_cfg1_deterministic_and_shape():
-    a = li.cfg1().boxes[0]
-    b = li.cfg1().boxes[0]
+def test_grid32_deterministic_and_shape():
+    a = li.points_32c_8s().boxes[0]
+    b = li.points_32c_8s().boxes[0]
     assert a.n == 32 and a.n_slices == 8 and a.supersample == 1
     np.testing.assert_array_equal(a.radii, np.arange(9) * 2.5)
     for (c1, l1), (c2, l2) in zip(a.sources, b.sources):
@@ -16,8 +16,8 @@ def test_cfg1_deterministic_and_shape():
         assert np.all(l1 > 0)
 
 
-def test_cfg3_counts():
-    cnt = li.cfg3_counts(40)
+def test_growing_counts():
+    cnt = li.growing_counts(40)
     assert cnt[0] == 46585 and cnt[-1] == 200
     assert sum(cnt) == 355816
 
@@ -30,8 +30,8 @@ def test_grf_top_fraction():
     assert np.all(lum > 0)
 
 
-def test_cfg5_mix():
-    w = li.cfg5()
+def test_uneven_mix():
+    w = li.uneven_16boxes()
     assert len(w.boxes) == 16
     for b in w.boxes:
         assert b.n in (64, 96, 128, 192, 256)

@@ -165,7 +165,7 @@ def test_kernel_cube_symmetries_and_real_spectrum(m):
 def test_flux_conservation_no_attenuation():
     """l^3 sum_c G_k(c) approximates the shell width r_{k+1} - r_k (the shell
     integral of 1/(4 pi r^2) over its volume)."""
-    w = li.cfg1()
+    w = li.points_32c_8s()
     b = w.boxes[0]
     l = b.box / b.n
     G4 = oracle.build_G(b.n, b.box, b.radii, 4, b.bands[0])
