@@ -65,6 +65,7 @@ def bytes_model(n, K, B, fused, csz, rsz):
     spec = n * n * (n // 2 + 1) * csz
     octb = (n // 2 + 1) ** 3 * rsz
     m = {
+        "xy_fwd": n3 * rsz + spec,            # fused x + y: read the grid, write the y-transformed spectrum
         "x_fwd": n3 * rsz + spec,             # read the source grid, write the half spectrum
         "col_y_fwd": 2 * spec,                # read + write one spectrum
         "col_y_inv": 2 * spec,
@@ -83,7 +84,8 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
     K = box.n_slices
     B = len(box.bands)
     n = box.n
-    plan = lc.Plan([box], precision=precision, use_graph=True)
+    fused = precision == lc.LC_PREC_FP32
+    plan = lc.Plan([box], precision=precision, use_graph=True, autotune=fused)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.build_all()
@@ -105,13 +107,18 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1) / steps
+    sched = plan.get_schedule(0)
     res = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "build_s": t_build,
-           "value": n ** 3 * K / (ms * 1e-3)}
+           "value": n ** 3 * K / (ms * 1e-3), "schedule": sched}
     if time_kernels:
-        fused = precision == lc.LC_PREC_FP32
-        ids = {"x_fwd": lc.LC_KERNEL_X_FWD, "col_y_fwd": lc.LC_KERNEL_COL_Y_FWD,
-               "col_y_inv": lc.LC_KERNEL_COL_Y_INV, "x_inv": lc.LC_KERNEL_X_INV}
-        per_step = {"x_fwd": K, "col_y_fwd": K, "col_y_inv": B, "x_inv": B}
+        if sched["xy_variant"] >= 0:
+            ids = {"xy_fwd": lc.LC_KERNEL_XY_FWD}
+            per_step = {"xy_fwd": K}
+        else:
+            ids = {"x_fwd": lc.LC_KERNEL_X_FWD, "col_y_fwd": lc.LC_KERNEL_COL_Y_FWD}
+            per_step = {"x_fwd": K, "col_y_fwd": K}
+        ids.update({"col_y_inv": lc.LC_KERNEL_COL_Y_INV, "x_inv": lc.LC_KERNEL_X_INV})
+        per_step.update({"col_y_inv": B, "x_inv": B})
         if fused:
             ids["fused_z"] = lc.LC_KERNEL_FUSED_Z
             per_step["fused_z"] = (B + 1) // 2
@@ -208,7 +215,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {desc}", "grid": n, "slices": K, "bands": len(box.bands),
                    "form": "FP32 butterflies, Kahan slice sum, FP64 twiddles/kernels/mean",
-                   "input": "dense FP32 source grids resident in HBM", "graph": True},
+                   "input": "dense FP32 source grids resident in HBM", "graph": True,
+                   "schedule": r32["schedule"]},
     }
     if args.no_kernel_times:
         print(json.dumps(line), flush=True)

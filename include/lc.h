@@ -105,7 +105,10 @@ typedef struct {
     void *workspace;              /* device memory, >= lc_workspace_bytes  */
     size_t workspace_bytes;
     int32_t use_graph;            /* 1: lc_step replays a captured graph   */
-    int32_t reserved;             /* must be 0                             */
+    int32_t autotune;             /* 1: lc_plan times every compiled launch
+                                     shape of the tunable passes on this
+                                     plan's buffers and keeps the fastest
+                                     (see lc_schedule); 0: built-in choice */
 } lc_plan_desc;
 
 /* Radial factor phi_b (Eqs. 14-17). G = prefactor * phi / (4 pi r^2).
@@ -207,14 +210,46 @@ typedef enum {
     LC_KERNEL_MAC = 4,        /* plain multiply-accumulate of one slice (unfused)     */
     LC_KERNEL_COL_Z_INV = 5,  /* inverse z pass of one band (unfused forms)           */
     LC_KERNEL_COL_Y_INV = 6,  /* inverse y pass of one band                           */
-    LC_KERNEL_X_INV = 7       /* inverse x pass + epilogue of one band                */
+    LC_KERNEL_X_INV = 7,      /* inverse x pass + epilogue of one band                */
+    LC_KERNEL_XY_FWD = 8      /* fused forward x + y pass of one slice (FP32 form,
+                                 N in {64, 96, 128, 192, 256}, where the step uses it
+                                 in place of LC_KERNEL_X_FWD + LC_KERNEL_COL_Y_FWD)   */
 } lc_kernel_id;
+
+/* Launch shapes of one box's tunable passes (a6: radix schedule, columns
+ * per tile and LDS layout are compiled per shape; the plan picks one).
+ *   xy_variant     fused forward x + y pass: shape in [0, n_xy), or -1 for
+ *                  separate x and y passes (always -1 when n_xy = 0)
+ *   fused_variant  fused z pass register schedule in [0, n_fused)
+ *                  (FP32 form; -1 in the other forms)
+ *   fused_rounds   1: persistent workgroups take whole tiles in rounds;
+ *                  0: the last round's tiles are split between two
+ *                  workgroups and merged by the inverse y pass
+ *   push_group     slices per batched forward launch in lc_step, 1..64
+ *   n_xy, n_fused  (lc_get_schedule only) shapes compiled for this N/form
+ * lc_set_schedule validates every field (LC_EINVAL) and applies them to
+ * later launches; the next lc_step captures a new graph. Changing whether
+ * the fused xy pass is used clears the box's pushed slices (they read as
+ * zero until pushed again). FP64 input grids (and point lists) always use
+ * xy shape 0. */
+typedef struct {
+    int32_t xy_variant;
+    int32_t fused_variant;
+    int32_t fused_rounds;
+    int32_t push_group;
+    int32_t n_xy;
+    int32_t n_fused;
+} lc_schedule;
+
+int lc_get_schedule(lc_plan_t *plan, int32_t box, lc_schedule *out);
+int lc_set_schedule(lc_plan_t *plan, int32_t box, const lc_schedule *s);
 
 /* Diagnostic: launch one kernel of the path `reps` times back to back on
  * the plan's stream and return the mean duration per launch measured with
  * HIP events recorded on that stream. Per-slice kernels cycle over the
- * box's slices; LC_KERNEL_X_FWD reads the dense device grid most recently
- * pushed for the slice (a zeroed scratch grid if none); per-band kernels
+ * box's slices; LC_KERNEL_X_FWD and LC_KERNEL_XY_FWD read the dense device
+ * grid most recently pushed for the slice (a zeroed scratch grid if none);
+ * per-band kernels
  * use band 0 (the fused pass handles bands 0-1); the output of
  * LC_KERNEL_X_INV goes to the workspace scratch. Kernels must be built.
  * The plan's spectra and accumulators are left unspecified: push every

@@ -28,10 +28,10 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", 
 
 EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_field",
             "lc_step", "lc_destroy", "lc_last_error", "lc_greens_imag_ratio", "lc_greens_dc",
-            "lc_time_kernel"]
+            "lc_time_kernel", "lc_get_schedule", "lc_set_schedule"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
- LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV) = range(8)
+ LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD) = range(9)
 
 
 class lc_box_desc(C.Structure):
@@ -44,7 +44,12 @@ class lc_plan_desc(C.Structure):
     _fields_ = [("n_boxes", C.c_int32), ("precision", C.c_int32),
                 ("boxes", C.POINTER(lc_box_desc)), ("hip_stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("use_graph", C.c_int32), ("autotune", C.c_int32)]
+
+
+class lc_schedule(C.Structure):
+    _fields_ = [("xy_variant", C.c_int32), ("fused_variant", C.c_int32), ("fused_rounds", C.c_int32),
+                ("push_group", C.c_int32), ("n_xy", C.c_int32), ("n_fused", C.c_int32)]
 
 
 class lc_atten(C.Structure):
@@ -91,8 +96,11 @@ def load():
     L.lc_greens_imag_ratio.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.lc_greens_dc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.lc_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.lc_get_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
+    L.lc_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
     for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_field", "lc_step",
-                 "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel"]:
+                 "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
+                 "lc_set_schedule"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -119,11 +127,11 @@ def make_box_desc(n: int, box: float, radii, n_bands: int = 1, supersample: int 
 
 
 def make_plan_desc(boxes: Sequence[lc_box_desc], precision: int, stream: int = 0,
-                   workspace: int = 0, workspace_bytes: int = 0, use_graph: int = 0):
+                   workspace: int = 0, workspace_bytes: int = 0, use_graph: int = 0, autotune: int = 0):
     arr = (lc_box_desc * len(boxes))(*boxes)
     d = lc_plan_desc(len(boxes), int(precision), C.cast(arr, C.POINTER(lc_box_desc)),
                      C.c_void_p(stream or None), C.c_void_p(workspace or None), int(workspace_bytes),
-                     int(use_graph), 0)
+                     int(use_graph), int(autotune))
     return d, arr
 
 
@@ -181,7 +189,8 @@ class Plan:
     conserve (e.g. lc_inputs.Box).
     """
 
-    def __init__(self, boxes, precision: int = LC_PREC_FP64, use_graph: bool = False, device=None):
+    def __init__(self, boxes, precision: int = LC_PREC_FP64, use_graph: bool = False, device=None,
+                 autotune: bool = False):
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
@@ -205,7 +214,7 @@ class Plan:
         self.stream = torch.cuda.Stream(device=self.device)
         self._enter()
         desc, arr2 = make_plan_desc(descs, precision, self.stream.cuda_stream, aligned, nbytes,
-                                    1 if use_graph else 0)
+                                    1 if use_graph else 0, 1 if autotune else 0)
         self._keep.append(arr2)
         self.handle = lc_plan(desc)
         self._leave()
@@ -285,6 +294,21 @@ class Plan:
         _check(load().lc_time_kernel(self.handle, box, kernel, reps, C.byref(v)))
         self._leave()
         return float(v.value)
+
+    def get_schedule(self, box: int = 0) -> dict:
+        """Launch shapes of one box's tunable passes (lc_get_schedule)."""
+        s = lc_schedule()
+        _check(load().lc_get_schedule(self.handle, box, C.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in lc_schedule._fields_}
+
+    def set_schedule(self, box: int = 0, **kw):
+        """Change some fields of a box's schedule (lc_set_schedule)."""
+        cur = self.get_schedule(box)
+        cur.update(kw)
+        s = lc_schedule(*[int(cur[f]) for f, _ in lc_schedule._fields_])
+        self._enter()
+        _check(load().lc_set_schedule(self.handle, box, C.byref(s)))
+        self._leave()
 
     def step(self, grids, outs, dtype=None):
         """One whole step (lc_step): push every slice of every box from dense

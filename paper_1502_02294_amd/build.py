@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblc.so")
 
-SOURCES = ["lc_fft.hip", "lc_field.hip", "lc_greens.hip", "lc_host.cpp"]
+SOURCES = ["lc_fft.hip", "lc_xy.hip", "lc_field.hip", "lc_greens.hip", "lc_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fno-fast-math",

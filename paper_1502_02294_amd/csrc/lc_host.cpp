@@ -229,10 +229,15 @@ struct BoxPlan {
     int *split_tab = nullptr;    // per band pair slot: tile -> part slot
     int64_t max_parts = 0, part_stride = 0, tiles = 0;
     int fused_variant = 0, fused_rounds = 1;
+    int xy_variant = 0;          // launch shape of the fused xy pass
+    int push_group = 2;          // slices per batched forward launch in lc_step
     unsigned long long *maxima = nullptr;
     char *tw_half = nullptr, *tw_full = nullptr, *twist = nullptr;       // plan precision
     char *tw64_half = nullptr, *tw64_full = nullptr, *twist64 = nullptr; // FP64 (builder)
     int xwgs = 0;
+    // FP32 form at N in {64, 96, 128, 192, 256}: x and y passes fused per plane
+    bool use_xy = false;
+    int dcw = 0;                 // FP64 DC partials per slice (x-pass workgroups or planes)
 };
 
 struct lc_plan_s {
@@ -242,7 +247,6 @@ struct lc_plan_s {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int use_graph = 0;
-    int push_group = 2;
     std::vector<BoxPlan> boxes;
     char *scratch_real = nullptr;    // FP64 N^3: builder grid / source staging / host-output staging
     char *scratch_spec = nullptr;    // FP64 spectrum for the builder
@@ -266,7 +270,7 @@ struct Layout {
 
 int validate(const lc_plan_desc *d) {
     if (!d) return fail(LC_EINVAL, "descriptor is NULL");
-    if (d->reserved != 0) return fail(LC_EINVAL, "reserved field must be 0");
+    if (d->autotune != 0 && d->autotune != 1) return fail(LC_EINVAL, "autotune must be 0 or 1");
     if (d->n_boxes < 1 || d->n_boxes > 4096) return fail(LC_EINVAL, "n_boxes must be in [1, 4096]");
     if (!d->boxes) return fail(LC_EINVAL, "boxes is NULL");
     if (d->precision != LC_PREC_FP64 && d->precision != LC_PREC_FP32_PLAIN && d->precision != LC_PREC_FP32)
@@ -322,7 +326,7 @@ Layout layout_of(const lc_plan_desc *d) {
         o.acc = take((size_t)B * spec_elems(n) * cs);
         o.ghat = take((size_t)K * B * oct_elems(n) * rs);
         o.ghat0 = take((size_t)K * B * 8);
-        o.dcpart = take((size_t)K * x_pass_wgs(n) * 8);
+        o.dcpart = take((size_t)K * std::max(x_pass_wgs(n), n) * 8);
         o.mu = take((size_t)B * 8);
         o.sk = take((size_t)K * 8);
         if (d->precision == LC_PREC_FP32) {
@@ -402,6 +406,134 @@ int valid_sources(const BoxPlan &bp, const lc_sources *s) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// Mean milliseconds per call of `launch`: one warm-up call, then `reps`
+// calls between two events recorded on the plan's stream.
+template <typename F> int time_calls(hipStream_t st, int reps, F &&launch, double *ms) {
+    HIPCHK(launch());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIPCHK(launch());
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return LC_OK;
+}
+
+FusedArgs fused_args(const BoxPlan &bp) {
+    FusedArgs fa;
+    const int n = bp.n;
+    fa.spec = bp.spec; fa.spec_stride = spec_elems(n); fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
+    fa.K = bp.K; fa.B = bp.B; fa.band0 = 0; fa.nband = std::min(2, bp.B);
+    fa.kcount[0] = bp.kcount[0]; fa.kcount[1] = bp.B > 1 ? bp.kcount[1] : 0;
+    fa.acc = bp.acc; fa.acc_stride = spec_elems(n); fa.zero_dc = 1; fa.kahan = 1;
+    fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
+    fa.split_tab = bp.split_tab;
+    fa.variant = bp.fused_variant;
+    fa.rounds = bp.fused_rounds;
+    return fa;
+}
+
+// Forward launch (fused xy pass with shape xyv >= 0, else x + y passes) of
+// `cnt` slices starting at output slice k0 of the box; the inputs are other
+// slices' spectrum memory read as FP32 grids (K >= 2 cnt), so successive
+// timed launches stream distinct memory as in a step.
+hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
+    const int n = bp.n;
+    const int64_t se = spec_elems(n);
+    SrcTab tab;
+    for (int j = 0; j < cnt; ++j)
+        tab.p[j] = bp.K >= 2 * cnt ? (const void *)(bp.spec + (size_t)((k0 + j + bp.K / 2) % bp.K) * se * 8)
+                                   : (const void *)p->scratch_real;
+    char *out = bp.spec + (size_t)k0 * se * 8;
+    double *dcp = bp.dcpart + (size_t)k0 * std::max(bp.n, bp.xwgs);
+    if (xyv >= 0)
+        return launch_xy_fwd_batch(n, tab, cnt, false, out, se, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.n, xyv,
+                                   p->stream);
+    hipError_t e = launch_x_fwd_batch(n, false, tab, cnt, false, out, se, bp.tw_half, bp.twist, dcp, p->stream);
+    if (e != hipSuccess) return e;
+    return launch_col_batch(n, false, 1, true, out, se, cnt, bp.tw_full, p->stream);
+}
+
+// Plan-time choice of the launch shapes of one FP32-form box (a6): every
+// compiled shape of the forward pass, the batching of the forward launches
+// and the fused z pass schedule is timed on this plan's buffers (all zero
+// at this point; the kernels' run time does not depend on the values) and
+// the fastest is kept. Spectra and DC partials are cleared afterwards.
+int autotune_box(lc_plan_t *p, BoxPlan &bp) {
+    const int n = bp.n;
+    const int reps = 3;
+    double best = 1e30, ms = 0.0;
+    int rot = 0;
+    // forward pass shape, per slice, at the default batching
+    {
+        const int g = std::max(1, std::min(bp.push_group, bp.K / 2));
+        int bestv = -1;
+        for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v) {
+            int rc = time_calls(p->stream, reps, [&]() {
+                const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
+                return tune_forward(p, bp, v, g, k0);
+            }, &ms);
+            if (rc) return rc;
+            if (ms < best) { best = ms; bestv = v; }
+        }
+        bp.xy_variant = bestv >= 0 ? bestv : 0;
+    }
+    // slices per forward launch
+    {
+        best = 1e30;
+        int bestg = bp.push_group;
+        for (int g = 1; g <= 16; g *= 2) {
+            if (g > std::max(1, bp.K / 2)) break;
+            int rc = time_calls(p->stream, reps, [&]() {
+                const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
+                return tune_forward(p, bp, bp.use_xy ? bp.xy_variant : -1, g, k0);
+            }, &ms);
+            if (rc) return rc;
+            if (ms / g < best) { best = ms / g; bestg = g; }
+        }
+        bp.push_group = bestg;
+    }
+    // fused z pass schedule and scheduling mode (with the inverse y pass
+    // that merges split tiles)
+    {
+        best = 1e30;
+        int bestv = bp.fused_variant, bestr = bp.fused_rounds;
+        for (int v = 0; v < fused_variants(n); ++v)
+            for (int r = 1; r >= 0; --r) {
+                bp.fused_variant = v;
+                bp.fused_rounds = r;
+                const FusedArgs fa = fused_args(bp);
+                int rc = time_calls(p->stream, 2, [&]() {
+                    hipError_t e = launch_fused_z(n, fa, bp.tw_full, p->stream);
+                    if (e != hipSuccess) return e;
+                    return launch_col_y_inv_combine(n, bp.acc, bp.tw_full, bp.split_tab, bp.part, p->stream);
+                }, &ms);
+                if (rc) return rc;
+                if (ms < best) { best = ms; bestv = v; bestr = r; }
+            }
+        bp.fused_variant = bestv;
+        bp.fused_rounds = bestr;
+    }
+    const size_t cs = 8;
+    HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
+    HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
+    return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t lc_workspace_bytes(const lc_plan_desc *desc) {
     if (validate(desc) != LC_OK) return 0;
     ok();
@@ -426,10 +558,6 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
     p->ws = (char *)d->workspace;
     p->ws_bytes = d->workspace_bytes;
     p->use_graph = d->use_graph;
-    if (const char *eg = std::getenv("LC_PUSH_GROUP")) {
-        const int g = std::atoi(eg);
-        if (g >= 1 && g <= SrcTab::kMax) p->push_group = g;
-    }
     p->scratch_real = p->ws + lay.scratch_real;
     p->scratch_spec = p->ws + lay.scratch_spec;
     const size_t cs = p->t_f64 ? 16 : 8;
@@ -462,16 +590,13 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             bp.part_stride = kMaxParts * x.n * fused_cpw(x.n);
             bp.tiles = fused_tiles(x.n);
             bp.fused_variant = fused_variants(x.n) > 2 ? 2 : 0;
-            if (const char *er = std::getenv("LC_FUSED_ROUNDS")) bp.fused_rounds = std::atoi(er) ? 1 : 0;
-            if (const char *ev = std::getenv("LC_FUSED_VARIANT")) {
-                const int v = std::atoi(ev);
-                if (v >= 0 && v < fused_variants(x.n)) bp.fused_variant = v;
-            }
         } bp.maxima = (unsigned long long *)(p->ws + o.maxima);
         bp.tw_half = p->ws + o.tw_half; bp.tw_full = p->ws + o.tw_full; bp.twist = p->ws + o.twist;
         bp.tw64_half = p->ws + o.tw64_half; bp.tw64_full = p->ws + o.tw64_full;
         bp.twist64 = p->ws + o.twist64;
         bp.xwgs = x_pass_wgs(bp.n);
+        bp.use_xy = p->prec == LC_PREC_FP32 && xy_supported(bp.n);
+        bp.dcw = bp.use_xy ? bp.n : bp.xwgs;
 
         // tables
         const int n = bp.n;
@@ -503,9 +628,28 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         }
         // slices never pushed are zero
         HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
-        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.xwgs, 0.0, p->stream));
+        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
         HIPCHK(launch_fill_f64(bp.ghat0, (int64_t)bp.K * bp.B, 0.0, p->stream));
         p->boxes.push_back(std::move(bp));
+    }
+    if (d->autotune && p->prec == LC_PREC_FP32) {
+        // boxes of equal N share the shapes measured on the first of them
+        std::vector<int> done_n;
+        std::vector<const BoxPlan *> done_bp;
+        for (auto &bp : p->boxes) {
+            size_t j = 0;
+            while (j < done_n.size() && done_n[j] != bp.n) ++j;
+            if (j < done_n.size()) {
+                bp.xy_variant = done_bp[j]->xy_variant;
+                bp.push_group = done_bp[j]->push_group;
+                bp.fused_variant = done_bp[j]->fused_variant;
+                bp.fused_rounds = done_bp[j]->fused_rounds;
+                continue;
+            }
+            if ((rc = autotune_box(p.get(), bp))) return rc;
+            done_n.push_back(bp.n);
+            done_bp.push_back(&bp);
+        }
     }
     HIPCHK(hipStreamSynchronize(p->stream));
     *out = p.release();
@@ -617,9 +761,16 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
     }
     const size_t cs = p->t_f64 ? 16 : 8;
     char *spec = bp.spec + (size_t)slice * spec_elems(n) * cs;
-    double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slice * bp.xwgs : nullptr;
-    HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, spec, bp.tw_half, bp.twist, dcp, st));
-    HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
+    double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slice * bp.dcw : nullptr;
+    if (bp.use_xy) {
+        SrcTab tab;
+        tab.p[0] = in;
+        HIPCHK(launch_xy_fwd_batch(n, tab, 1, in_f64, spec, 0, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.dcw,
+                                   bp.xy_variant, st));
+    } else {
+        HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, spec, bp.tw_half, bp.twist, dcp, st));
+        HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
+    }
     if (p->prec != LC_PREC_FP32) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
     bp.pushed[slice] = 1;
     return LC_OK;
@@ -645,7 +796,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
     const double inv_n3 = 1.0 / ((double)n * n * n);
     hipStream_t st = p->stream;
     if (p->prec == LC_PREC_FP32) {
-        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.xwgs, bp.ghat0, bp.B, inv_n3, bp.sk, bp.mu, st));
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.ghat0, bp.B, inv_n3, bp.sk, bp.mu, st));
         for (int b = b0; b < b1;) {
             const int nb = std::min(2, b1 - b);
             int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;
@@ -751,7 +902,7 @@ static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int
             }
             int cnt = 0;
             SrcTab tab;
-            while (k + cnt < bp.K && cnt < p->push_group && srcs[si + k + cnt].kind == 0 &&
+            while (k + cnt < bp.K && cnt < bp.push_group && srcs[si + k + cnt].kind == 0 &&
                    srcs[si + k + cnt].dtype == s0.dtype) {
                 tab.p[cnt] = srcs[si + k + cnt].grid;
                 bp.last_src[k + cnt] = srcs[si + k + cnt].grid;
@@ -759,10 +910,15 @@ static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int
                 ++cnt;
             }
             char *spec = bp.spec + (size_t)k * se * cs;
-            double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.xwgs : nullptr;
-            HIPCHK(launch_x_fwd_batch(n, p->t_f64, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist,
-                                      dcp, p->stream));
-            HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, p->stream));
+            double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.dcw : nullptr;
+            if (bp.use_xy) {
+                HIPCHK(launch_xy_fwd_batch(n, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist,
+                                           bp.tw_full, dcp, bp.dcw, bp.xy_variant, p->stream));
+            } else {
+                HIPCHK(launch_x_fwd_batch(n, p->t_f64, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half,
+                                          bp.twist, dcp, p->stream));
+                HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, p->stream));
+            }
             if (p->prec != LC_PREC_FP32)
                 HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, p->stream));
             for (int j = 0; j < cnt; ++j) bp.pushed[k + j] = 1;
@@ -860,14 +1016,17 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
         if (!bp.built[b]) return fail(LC_ESTATE, "kernels not built");
     const bool fused = p->prec == LC_PREC_FP32;
     const bool plain_only = kernel == LC_KERNEL_COL_Z_FWD || kernel == LC_KERNEL_MAC || kernel == LC_KERNEL_COL_Z_INV;
-    if (kernel < 0 || kernel > LC_KERNEL_X_INV) return fail(LC_EINVAL, "unknown kernel id %d", kernel);
+    if (kernel < 0 || kernel > LC_KERNEL_XY_FWD) return fail(LC_EINVAL, "unknown kernel id %d", kernel);
+    if (kernel == LC_KERNEL_XY_FWD && !bp.use_xy)
+        return fail(LC_EINVAL, "this plan does not use the fused xy pass (FP32 form, N in 64..256)");
     if (fused && plain_only) return fail(LC_EINVAL, "kernel %d is not part of the fused form", kernel);
     if (!fused && kernel == LC_KERNEL_FUSED_Z) return fail(LC_EINVAL, "the fused z pass belongs to LC_PREC_FP32");
     const int n = bp.n;
     const int64_t n3 = (int64_t)n * n * n, se = spec_elems(n);
     const size_t cs = p->t_f64 ? 16 : 8, rs = p->t_f64 ? 8 : 4;
     hipStream_t st = p->stream;
-    if (kernel == LC_KERNEL_X_FWD) HIPCHK(launch_fill_bytes(p->scratch_real, n3 * (int64_t)rs, st));
+    if (kernel == LC_KERNEL_X_FWD || kernel == LC_KERNEL_XY_FWD)
+        HIPCHK(launch_fill_bytes(p->scratch_real, n3 * (int64_t)rs, st));
     // per-slice kernels cycle over the slices (inputs of the most recent
     // pushes where known) so that their data stream from memory as in a step
     int rep = 0;
@@ -879,7 +1038,14 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                 const void *in = bp.last_src[k] ? bp.last_src[k] : p->scratch_real;
                 const bool in_f64 = bp.last_src[k] ? bp.last_src_f64[k] != 0 : p->t_f64;
                 return launch_x_fwd(n, p->t_f64, in, in_f64, speck, bp.tw_half, bp.twist,
-                                    fused ? bp.dcpart + (size_t)k * bp.xwgs : nullptr, st);
+                                    fused && !bp.use_xy ? bp.dcpart + (size_t)k * bp.dcw : nullptr, st);
+            }
+            case LC_KERNEL_XY_FWD: {
+                SrcTab tab;
+                tab.p[0] = bp.last_src[k] ? bp.last_src[k] : p->scratch_real;
+                const bool in_f64 = bp.last_src[k] ? bp.last_src_f64[k] != 0 : false;
+                return launch_xy_fwd_batch(n, tab, 1, in_f64, speck, 0, bp.tw_half, bp.twist, bp.tw_full,
+                                           bp.dcpart + (size_t)k * bp.dcw, bp.dcw, bp.xy_variant, st);
             }
             case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, speck, bp.tw_full, st);
             case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, speck, bp.tw_full, st);
@@ -920,6 +1086,52 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / reps;
+    return ok();
+}
+
+int lc_get_schedule(lc_plan_t *p, int32_t box, lc_schedule *out) {
+    if (!p || !out) return fail(LC_EINVAL, "NULL argument");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box out of range");
+    const BoxPlan &bp = p->boxes[box];
+    const bool fused = p->prec == LC_PREC_FP32;
+    out->n_xy = fused ? xy_variants(bp.n) : 0;
+    out->n_fused = fused ? fused_variants(bp.n) : 0;
+    out->xy_variant = bp.use_xy ? bp.xy_variant : -1;
+    out->fused_variant = fused ? bp.fused_variant : -1;
+    out->fused_rounds = bp.fused_rounds;
+    out->push_group = bp.push_group;
+    return ok();
+}
+
+int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
+    if (!p || !s) return fail(LC_EINVAL, "NULL argument");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box out of range");
+    BoxPlan &bp = p->boxes[box];
+    const bool fused = p->prec == LC_PREC_FP32;
+    const int n_xy = fused ? xy_variants(bp.n) : 0, n_fused = fused ? fused_variants(bp.n) : 0;
+    if (s->xy_variant < -1 || s->xy_variant >= n_xy)
+        return fail(LC_EINVAL, "xy_variant %d outside [-1, %d)", s->xy_variant, n_xy);
+    if (fused ? (s->fused_variant < 0 || s->fused_variant >= n_fused) : s->fused_variant != -1)
+        return fail(LC_EINVAL, "fused_variant %d not available", s->fused_variant);
+    if (s->fused_rounds != 0 && s->fused_rounds != 1) return fail(LC_EINVAL, "fused_rounds must be 0 or 1");
+    if (s->push_group < 1 || s->push_group > SrcTab::kMax)
+        return fail(LC_EINVAL, "push_group must be in [1, %d]", SrcTab::kMax);
+    const bool use_xy = s->xy_variant >= 0;
+    if (use_xy != bp.use_xy) {
+        // the DC partial layout changes with the forward pass: pushed slices are dropped
+        bp.use_xy = use_xy;
+        bp.dcw = use_xy ? bp.n : bp.xwgs;
+        const size_t cs = p->t_f64 ? 16 : 8;
+        HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(bp.n) * cs, p->stream));
+        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
+        std::fill(bp.pushed.begin(), bp.pushed.end(), 0);
+        std::fill(bp.last_src.begin(), bp.last_src.end(), nullptr);
+    }
+    if (use_xy) bp.xy_variant = s->xy_variant;
+    if (fused) bp.fused_variant = s->fused_variant;
+    bp.fused_rounds = s->fused_rounds;
+    bp.push_group = s->push_group;
+    p->gkey.clear();   // the next lc_step captures the new launch sequence
     return ok();
 }
 

@@ -38,6 +38,17 @@ struct SrcTab {
 hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bool in_f64, void *spec,
                               int64_t spec_stride, const void *tw_half, const void *twist, double *dcpart,
                               hipStream_t st);
+// Fused forward x + y pass of `count` slices (FP32 form, N in {64, 96, 128,
+// 192, 256}; xy_supported): one workgroup per z-plane. Slice i reads in.p[i],
+// writes its y-transformed spectrum at spec + i*spec_stride and one FP64 sum
+// of the input per plane at dcpart + i*dc_stride + z.
+// `variant` selects one of xy_variants(n) compiled launch shapes (FP64
+// input always runs shape 0).
+bool xy_supported(int n);
+int xy_variants(int n);
+hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
+                               const void *tw_half, const void *twist, const void *tw_full, double *dcpart,
+                               int64_t dc_stride, int variant, hipStream_t st);
 // Column pass over `count` spectra at spec + i*stride (complex elements).
 hipError_t launch_col_batch(int n, bool t_f64, int axis, bool fwd, void *spec, int64_t stride, int count,
                             const void *tw_full, hipStream_t st);

@@ -1,0 +1,305 @@
+// Forward x and y passes of the 3D transform of Eq. 12 fused per z-plane,
+// for the FP32 form at N in {64, 96, 128, 192, 256}.
+//
+// One workgroup owns one z-plane of one slice (N x N reals, at N = 256 a
+// 256 KiB plane whose half spectrum is 264 KiB): it reads the plane once,
+// keeps it in registers between the two transforms and writes the
+// y-transformed half spectrum once. Against separate x and y passes this
+// removes one full write and one full read of the spectrum per slice.
+//
+//   1. Every row is read (all row batches issued up front) as N/2 complex
+//      values z[n] = x[2n] + i x[2n+1] and transformed by the N/2-point
+//      register-in/register-out engine, RPB rows at a time.
+//   2. The real-to-half-spectrum untangle runs in registers: the partner
+//      Z[N/2 - q] of the element at position q is held by lane TX - t of the
+//      same row at an element index fixed at compile time (see partner_e),
+//      so one lane shuffle per element replaces an LDS round trip:
+//        E = (Z[q] + conj Z[L-q]) / 2,  O = (Z[q] - conj Z[L-q]) / (2i),
+//        Y[q] = E + W^q O,    W = exp(-2 pi i / N).
+//   3. The p = 0 and p = N/2 columns are real for real input; they travel
+//      through the y transform packed as one complex column
+//      C = Y[.][0] + i Y[.][N/2], so the y pass has exactly N/2 columns, and
+//      are separated afterwards:
+//        Y^[k][0] = (C^[k] + conj C^[N-k]) / 2,
+//        Y^[k][N/2] = (C^[k] - conj C^[N-k]) / (2i).
+//   4. Column batch by column batch, the plane is transposed through LDS
+//      (layout [row][column], one pad column) and each column of N values is
+//      transformed by the N-point engine; lanes walk the columns, so every
+//      store instruction writes 64 consecutive complex values of a row.
+//
+// The FP64 sum of the input plane (the DC mode of Eq. 12, kept in FP64 for
+// the FP32 form) is written per plane to dcpart.
+#include <type_traits>
+
+#include "lc_fft_device.h"
+#include "lc_internal.h"
+
+namespace lc {
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, C - 1>): the
+// batch index stays a compile-time constant, so register arrays indexed by
+// it are never demoted to scratch memory, however large the loop body.
+template <int C, int I = 0, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < C) {
+        f(std::integral_constant<int, I>{});
+        static_for<C, I + 1>(f);
+    }
+}
+
+// Launch shape: S8 selects the 8-elements-per-thread schedules (smaller
+// register working set, one more LDS exchange per line), NB_ the number of
+// row batches of the x phase (= column batches of the y phase), NC_ the
+// number of column batches that the x phase deposits straight into LDS
+// regions of their own (the rest of the plane waits in registers).
+template <int N, bool S8, int NB_, int NC_> struct XYShape {
+    static constexpr int L = N / 2;
+    using SX = std::conditional_t<S8, Sched8<L>, Sched<L>>;
+    using SY = std::conditional_t<S8, Sched8<N>, Sched<N>>;
+    static constexpr int TX = SX::TPL, TY = SY::TPL;
+    static constexpr int NB = NB_;
+    static constexpr int RPB = N / NB;            // rows per x batch
+    static constexpr int CPB = L / NB;            // complex columns per y batch
+    static constexpr int NT = TX * RPB;
+    static constexpr int SK = 4;                  // x lines: one pad slot every 16 elements
+    static constexpr int LSX = L + (L >> SK) + 1;
+    static constexpr int ES = CPB + 1;            // y: LDS row stride of the transposed batch
+    static constexpr int NC = NC_;
+    static constexpr int LDS_X = RPB * LSX;
+    static constexpr int RG = N * ES;                     // one transposed column batch
+    static constexpr int XS = LDS_X > RG ? LDS_X : RG;    // x scratch, then y batches >= NC
+    static constexpr int LDS = XS + NC * RG;
+    static_assert(NC >= 0 && NC <= NB, "column batches held in LDS");
+    static_assert((LDS + 2 * L + 2 * N) * 8 + NT / 8 <= 160 * 1024, "LDS of one workgroup");
+    static_assert(NT == TY * CPB, "x and y phases must use the same thread count");
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole waves, one workgroup");
+    static_assert(CPB % TX == 0, "column batches must hold whole lane groups of a row");
+};
+
+// Element index, in the same thread or in lane TX - t, holding the partner
+// position L - q of the element e of the last x pass. Output positions of the
+// last pass are q = t + i*TX + r*M (e = i*RL + r, M = L/RL = BPT*TX).
+template <int RL, int BPT>
+__device__ __forceinline__ constexpr int partner_e(int e, bool t0) {
+    const int i = e / RL, r = e % RL;
+    if (!t0) return (BPT - 1 - i) * RL + (RL - 1 - r);
+    if (i > 0) return (BPT - i) * RL + (RL - 1 - r);
+    return (RL - r) % RL;
+}
+
+// Pin a value to the point where it is computed: an empty volatile asm
+// statement that claims to modify the registers (no instruction is emitted).
+// Without it the compiler sinks the untangle arithmetic and the FP64 input
+// sum of every row batch down to their uses in the y phase, which keeps the
+// inputs of all batches live together and spills them.
+__device__ __forceinline__ void pin(cx<float> &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+template <int N, typename TIN, bool S8, int NB_, int NC_>
+__global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
+    SrcTab srcs, cx<float> *__restrict__ spec0, int64_t spec_stride, const cx<float> *__restrict__ tw_half,
+    const cx<float> *__restrict__ twist, const cx<float> *__restrict__ tw_full, double *__restrict__ dcpart,
+    int64_t dc_stride) {
+    using SH = XYShape<N, S8, NB_, NC_>;
+    constexpr int L = SH::L, TX = SH::TX, NB = SH::NB, RPB = SH::RPB, CPB = SH::CPB, NT = SH::NT;
+    constexpr int SK = SH::SK, LSX = SH::LSX, ES = SH::ES, NC = SH::NC, XS = SH::XS, RG = SH::RG;
+    // row batches in flight ahead of the transform (FP64 input loads are twice as wide)
+    constexpr int PF = NB < 2 ? NB : (std::is_same<TIN, float>::value ? 2 : 1);
+    using EX = Engine<float, L, true, typename SH::SX, SK>;
+    using EY = Engine<float, N, true, typename SH::SY>;
+    constexpr int EXN = EX::E, EYN = EY::E;
+    constexpr int RL = EX::RL, BPTL = EX::PLs::BPT, M = L / RL;
+    static_assert(BPTL * TX == M, "last x pass layout");
+
+    __shared__ cx<float> lds[SH::LDS];
+    __shared__ cx<float> twx[L], twt[L], twy[N];
+    __shared__ cx<float> zb[N];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    const int slice = blockIdx.x / N, z = blockIdx.x % N;
+    const TIN *__restrict__ in = (const TIN *)srcs.p[slice] + (int64_t)z * N * N;
+    cx<float> *__restrict__ mainp = spec0 + slice * spec_stride + (int64_t)z * N * L;
+    cx<float> *__restrict__ nyq = spec0 + slice * spec_stride + spec_main(N) + (int64_t)z * N;
+
+    // ---- 1. rows of the plane (row batch b, row xl of the batch), read PF
+    //         batches ahead of their transform
+    const int xl = tid / TX, xt = tid % TX;
+    cx<float> xr[NB][EXN];
+    double dsum = 0.0;
+    auto load_batch = [&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (b < NB) {
+            const TIN *row = in + (int64_t)(b * RPB + xl) * N;
+#pragma unroll
+            for (int e = 0; e < EXN; ++e) {
+                const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
+                xr[b][e] = mk((float)v.x, (float)v.y);
+            }
+        }
+    };
+    static_for<PF>(load_batch);
+    for (int i = tid; i < L; i += NT) {
+        twx[i] = tw_half[i];
+        twt[i] = twist[i];
+    }
+    for (int i = tid; i < N; i += NT) twy[i] = tw_full[i];
+
+    // ---- 2. x transforms and untangle, one row batch at a time
+    const int lane = tid & 63;
+    const int partner_lane = (lane & ~(TX - 1)) | ((TX - xt) & (TX - 1));
+    const bool t0 = xt == 0;
+    static_for<NB>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        load_batch(std::integral_constant<int, b + PF>{});
+        if constexpr (std::is_same<TIN, float>::value) {
+            // FP32 input converts exactly: sum it here, before the batch is
+            // transformed, so the raw values need not stay live
+#pragma unroll
+            for (int e = 0; e < EXN; ++e) dsum += (double)xr[b][e].x + (double)xr[b][e].y;
+            pin(dsum);
+        }
+        EX::run(xr[b], lds, xl * LSX, 1, xt, twx);
+        cx<float> pv[EXN];
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            const cx<float> s = xr[b][partner_e<RL, BPTL>(e, false)];
+            cx<float> o;
+            o.x = __shfl(s.x, partner_lane, 64);
+            o.y = __shfl(s.y, partner_lane, 64);
+            pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
+        }
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            const int q = EX::out_pos(xt, e);
+            const cx<float> A = xr[b][e], B = pv[e];
+            const cx<float> Ev = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
+            const cx<float> O = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
+            if (e == 0 && t0) {
+                // q = 0: Y[0] = Re A + Im A and Y[L] = Re A - Im A, both real: packed
+                xr[b][e] = mk(A.x + A.y, A.x - A.y);
+            } else {
+                xr[b][e] = Ev + cmul(twt[q], O);
+            }
+            pin(xr[b][e]);
+        }
+        if constexpr (NC > 0) {
+            // elements of the first NC column batches go to their LDS regions now
+            const int row = b * RPB + xl;
+#pragma unroll
+            for (int e = 0; e < EXN; ++e) {
+                const int i = e / RL, r = e % RL;
+                const int cb = (r * M + i * TX) / CPB;
+                if (cb < NC) lds[XS + cb * RG + row * ES + (EX::out_pos(xt, e) - cb * CPB)] = xr[b][e];
+            }
+        }
+    });
+
+    // ---- 3. y transforms, one column batch at a time
+    const int yc = tid % CPB, yt = tid / CPB;
+    static_for<NB>([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
+        // transposed batch: its own region (filled by the x phase) or the scratch
+        cx<float> *reg = cb < NC ? lds + XS + cb * RG : lds;
+        if constexpr (cb >= NC) {
+            lds_barrier();   // earlier readers of the scratch are done
+            static_for<NB>([&](auto bc) {
+                constexpr int b = decltype(bc)::value;
+                const int row = b * RPB + xl;
+#pragma unroll
+                for (int e = 0; e < EXN; ++e) {
+                    const int i = e / RL, r = e % RL;
+                    if ((r * M + i * TX) / CPB == cb) {
+                        const int q = EX::out_pos(xt, e);
+                        reg[row * ES + (q - cb * CPB)] = xr[b][e];
+                    }
+                }
+            });
+        }
+        lds_barrier();
+        cx<float> y[EYN];
+#pragma unroll
+        for (int e = 0; e < EYN; ++e) y[e] = reg[EY::in_pos(yt, e) * ES + yc];
+        EY::run(y, reg, yc, ES, yt, twy);
+        const int p = cb * CPB + yc;
+        if (p != 0) {
+#pragma unroll
+            for (int e = 0; e < EYN; ++e) mainp[(int64_t)EY::out_pos(yt, e) * L + p] = y[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < EYN; ++e) zb[EY::out_pos(yt, e)] = y[e];
+        }
+    });
+
+    // ---- 4. separate the packed p = 0 / p = N/2 column; FP64 plane sum
+    if constexpr (!std::is_same<TIN, float>::value) {
+        // FP64 input: the sum needs the values before rounding; read them again
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const TIN *row = in + (int64_t)(b * RPB + xl) * N;
+            for (int e = 0; e < EXN; ++e) {
+                const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
+                dsum += (double)v.x + (double)v.y;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
+    if (lane == 0) red[tid >> 6] = dsum;
+    lds_barrier();
+    for (int k = tid; k < N; k += NT) {
+        const cx<float> A = zb[k], B = zb[(N - k) % N];
+        mainp[(int64_t)k * L] = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
+        nyq[k] = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
+    }
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        dcpart[slice * dc_stride + z] = s;
+    }
+}
+
+bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
+
+// Launch shapes compiled per N (schedule, batches); the plan picks one.
+int xy_variants(int n) { return n == 256 ? 3 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
+
+template <int N, typename TIN, bool S8, int NB, int NC>
+static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_stride, const void *tw_half,
+                       const void *twist, const void *tw_full, double *dcpart, int64_t dc_stride,
+                       hipStream_t st) {
+    using SH = XYShape<N, S8, NB, NC>;
+    hipLaunchKernelGGL((xy_fwd_kernel<N, TIN, S8, NB, NC>), dim3((unsigned)(N * count)), dim3(SH::NT), 0, st, in,
+                       (cx<float> *)spec, spec_stride, (const cx<float> *)tw_half, (const cx<float> *)twist,
+                       (const cx<float> *)tw_full, dcpart, dc_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
+                               const void *tw_half, const void *twist, const void *tw_full, double *dcpart,
+                               int64_t dc_stride, int variant, hipStream_t st) {
+    if (count < 1 || count > SrcTab::kMax || !dcpart) return hipErrorInvalidValue;
+    if (variant < 0 || variant >= xy_variants(n)) return hipErrorInvalidValue;
+    if (in_f64) variant = 0;   // the FP64-input instances of the other shapes spill
+#define X_(N, S8, NB, NC)                                                                                      \
+    return in_f64 ? xy_t<N, double, S8, NB, NC>(in, count, spec, spec_stride, tw_half, twist, tw_full, dcpart, \
+                                                dc_stride, st)                                                 \
+                  : xy_t<N, float, S8, NB, NC>(in, count, spec, spec_stride, tw_half, twist, tw_full, dcpart,  \
+                                               dc_stride, st);
+    switch (n) {
+        case 64: X_(64, false, 1, 0)
+        case 96: X_(96, false, 1, 0)
+        case 128:
+            if (variant == 0) { X_(128, false, 1, 0) }
+            X_(128, true, 2, 0)
+        case 192:
+            if (variant == 0) { X_(192, false, 4, 3) }
+            X_(192, false, 4, 0)
+        case 256:
+            if (variant == 0) { X_(256, true, 8, 3) }
+            if (variant == 1) { X_(256, false, 4, 1) }
+            X_(256, true, 4, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef X_
+}
+
+}  // namespace lc

@@ -45,7 +45,7 @@ def _desc(n=32, box=20.0, K=4, m=1, radii=None, prec=0, ws=0, wsb=0, bands=1, **
     for f in ("reserved",):
         if f in kw:
             setattr(d, f, kw[f])
-    pd, arr = lc.make_plan_desc([d], prec, 0, ws, wsb, kw.get("use_graph", 0))
+    pd, arr = lc.make_plan_desc([d], prec, 0, ws, wsb, kw.get("use_graph", 0), kw.get("autotune", 0))
     return pd, (keep, arr)
 
 
@@ -80,6 +80,7 @@ def test_workspace_bytes_scales_with_problem():
     (dict(box=-1.0), "LC_EINVAL"),
     (dict(prec=7), "LC_EINVAL"),
     (dict(reserved=3), "LC_EINVAL"),
+    (dict(autotune=2), "LC_EINVAL"),
 ])
 def test_invalid_descriptors_rejected_before_device(case, code):
     lc = _lc()
@@ -124,6 +125,8 @@ def test_null_handles_and_last_error():
     assert L.lc_field(None, 0, 0, None, 0, 0) == lc.LC_EINVAL
     assert L.lc_step(None, None, None, 0) == lc.LC_EINVAL
     assert L.lc_time_kernel(None, 0, 0, 1, None) == lc.LC_EINVAL
+    assert L.lc_get_schedule(None, 0, None) == lc.LC_EINVAL
+    assert L.lc_set_schedule(None, 0, None) == lc.LC_EINVAL
     L.lc_destroy(None)          # no-op
 
 
@@ -136,7 +139,8 @@ def test_struct_layouts_match_header():
 #include "lc.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(lc_box_desc), offsetof(lc_box_desc, box), offsetof(lc_box_desc, radii), offsetof(lc_box_desc, reserved));
-  printf("%zu %zu %zu %zu %zu\n", sizeof(lc_plan_desc), offsetof(lc_plan_desc, hip_stream), offsetof(lc_plan_desc, workspace_bytes), offsetof(lc_plan_desc, use_graph), offsetof(lc_plan_desc, boxes));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lc_plan_desc), offsetof(lc_plan_desc, hip_stream), offsetof(lc_plan_desc, workspace_bytes), offsetof(lc_plan_desc, use_graph), offsetof(lc_plan_desc, boxes), offsetof(lc_plan_desc, autotune));
+  printf("%zu %zu %zu\n", sizeof(lc_schedule), offsetof(lc_schedule, push_group), offsetof(lc_schedule, n_fused));
   printf("%zu %zu %zu\n", sizeof(lc_atten), offsetof(lc_atten, a), offsetof(lc_atten, prefactor));
   printf("%zu %zu %zu %zu\n", sizeof(lc_sources), offsetof(lc_sources, grid), offsetof(lc_sources, n), offsetof(lc_sources, lum));
   return 0;
@@ -155,9 +159,11 @@ int main(void) {
     p = list(map(int, out[1].split()))
     assert p == [C.sizeof(lc.lc_plan_desc), lc.lc_plan_desc.hip_stream.offset,
                  lc.lc_plan_desc.workspace_bytes.offset, lc.lc_plan_desc.use_graph.offset,
-                 lc.lc_plan_desc.boxes.offset]
-    a = list(map(int, out[2].split()))
+                 lc.lc_plan_desc.boxes.offset, lc.lc_plan_desc.autotune.offset]
+    sc = list(map(int, out[2].split()))
+    assert sc == [C.sizeof(lc.lc_schedule), lc.lc_schedule.push_group.offset, lc.lc_schedule.n_fused.offset]
+    a = list(map(int, out[3].split()))
     assert a == [C.sizeof(lc.lc_atten), lc.lc_atten.a.offset, lc.lc_atten.prefactor.offset]
-    s = list(map(int, out[3].split()))
+    s = list(map(int, out[4].split()))
     assert s == [C.sizeof(lc.lc_sources), lc.lc_sources.grid.offset, lc.lc_sources.n.offset,
                  lc.lc_sources.lum.offset]

@@ -1,0 +1,163 @@
+"""GPU parity of the fused forward x + y pass and of the launch-shape choice.
+
+Every compiled shape of the fused xy pass (and the separate x and y passes
+it replaces) is run at every grid size it supports, in the FP32 form, and
+compared with the CPU FP64 oracle (route D): on the full grid up to N = 96,
+on seeded sampled cells above. Tolerance: the FP32 form's e_rms <= 1e-5
+(normwise) with e_max <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import lc_inputs as li
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lc():
+    import paper_1502_02294_amd as lc
+    return lc
+
+
+def _box(n, K=3, m=2, seed=11, count=150):
+    L = 0.78125 * n
+    radii = np.linspace(0.0, 0.45 * L, K + 1)
+    srcs = [li.random_sources([seed, n, k], n, count) for k in range(K)]
+    return li.Box(n=n, box=L, radii=radii, supersample=m, bands=[li.Atten(kind=0)], sources=srcs)
+
+
+def _targets(n):
+    if n <= 96:
+        return np.arange(n ** 3, dtype=np.int64)
+    return li.sample_cells([7, n], n, 3000)
+
+
+def _oracle(box, targets):
+    """Route D: dense kernel for the small grids (full-grid targets), the
+    kernel evaluated from its definition for sampled cells of large grids."""
+    if box.n <= 96:
+        G = oracle.build_G(box.n, box.box, box.radii, box.supersample, box.bands[0])
+        return oracle.field_direct(G, box.sources, targets)
+    return oracle.field_direct_ondemand(box.n, box.box, box.radii, box.supersample, box.bands[0],
+                                        box.sources, targets)
+
+
+def _field(plan, box, dense=True):
+    keep = []
+    for k, (cells, lum) in enumerate(box.sources):
+        if dense:
+            g = torch.from_numpy(li.dense_grid(box.n, cells, lum, np.float32)).cuda()
+            keep.append(plan.push_grid(0, k, g))
+        else:
+            keep.append(plan.push_points(0, k, torch.from_numpy(cells).cuda(),
+                                         torch.from_numpy(lum).cuda()))
+    J = plan.field(0, 0).double().cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    return J
+
+
+@pytest.mark.parametrize("n", [64, 96, 128, 192, 256])
+def test_every_xy_shape_against_oracle(n):
+    lc = _lc()
+    box = _box(n)
+    tg = _targets(n)
+    Jr = _oracle(box, tg)
+    plan = lc.Plan([box], precision=lc.LC_PREC_FP32)
+    plan.build_all()
+    sch = plan.get_schedule(0)
+    assert sch["n_xy"] >= 1 and 0 <= sch["xy_variant"] < sch["n_xy"]
+    for v in list(range(sch["n_xy"])) + [-1]:
+        print(f"case n={n} xy_variant={v}", flush=True)
+        plan.set_schedule(0, xy_variant=v)
+        assert plan.get_schedule(0)["xy_variant"] == v
+        J = _field(plan, box)
+        e_max, e_rms = oracle.rel_errors(J[tg], Jr)
+        print(f"n={n} xy_variant={v} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+        assert e_rms <= 1e-5 and e_max <= 1e-4
+    # FP64 point lists take the FP64-input instance of the pass
+    plan.set_schedule(0, xy_variant=0)
+    print(f"case n={n} point lists", flush=True)
+    J = _field(plan, box, dense=False)
+    e_max, e_rms = oracle.rel_errors(J[tg], Jr)
+    print(f"n={n} points e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+    assert e_rms <= 1e-5 and e_max <= 1e-4
+    plan.close()
+
+
+def test_xy_batched_step_and_empty_planes():
+    """lc_step groups slices into one xy launch; an all-zero slice and a
+    slice whose sources sit in one z-plane exercise the per-plane DC sums."""
+    lc = _lc()
+    n, K = 128, 5
+    box = _box(n, K=K)
+    cells = np.array([5 * n * n + 3 * n + 7, 5 * n * n + 100, 5 * n * n + n * n - 1], np.int64)
+    box.sources[1] = (cells, np.array([2.0, 0.5, 1.25]))
+    box.sources[3] = (np.zeros(0, np.int64), np.zeros(0))
+    tg = _targets(n)
+    Jr = _oracle(box, tg)
+    plan = lc.Plan([box], precision=lc.LC_PREC_FP32, use_graph=True)
+    plan.build_all()
+    grids = [torch.from_numpy(li.dense_grid(n, c, v, np.float32)).cuda() for c, v in box.sources]
+    for g in (1, 2, 4):
+        plan.set_schedule(0, push_group=g)
+        out = [torch.empty((n, n, n), dtype=torch.float32, device="cuda")]
+        print(f"case step push_group={g}", flush=True)
+        plan.step(grids, out)
+        J = out[0].double().cpu().numpy().ravel()
+        e_max, e_rms = oracle.rel_errors(J[tg], Jr)
+        print(f"push_group={g} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+        assert e_rms <= 1e-5 and e_max <= 1e-4
+    plan.close()
+
+
+def test_autotune_two_sizes_one_step():
+    """autotune = 1 times every shape at plan time; boxes of one N share the
+    choice; the tuned step still matches the oracle."""
+    lc = _lc()
+    boxes = [_box(64, K=4, seed=21), _box(96, K=2, seed=22), _box(64, K=3, seed=23)]
+    print("case autotune plan", flush=True)
+    plan = lc.Plan(boxes, precision=lc.LC_PREC_FP32, use_graph=True, autotune=True)
+    plan.build_all()
+    s0, s2 = plan.get_schedule(0), plan.get_schedule(2)
+    for key in ("xy_variant", "fused_variant", "fused_rounds", "push_group"):
+        assert s0[key] == s2[key]
+    for bi in range(3):
+        s = plan.get_schedule(bi)
+        assert 0 <= s["xy_variant"] < s["n_xy"] and 0 <= s["fused_variant"] < s["n_fused"]
+        assert s["fused_rounds"] in (0, 1) and 1 <= s["push_group"] <= 64
+    grids, outs = [], []
+    for b in boxes:
+        for c, v in b.sources:
+            grids.append(torch.from_numpy(li.dense_grid(b.n, c, v, np.float32)).cuda())
+        outs.append(torch.empty((b.n,) * 3, dtype=torch.float32, device="cuda"))
+    plan.step(grids, outs)
+    torch.cuda.synchronize()
+    for b, o in zip(boxes, outs):
+        tg = li.sample_cells([3, b.n], b.n, 2000)
+        e_max, e_rms = oracle.rel_errors(o.double().cpu().numpy().ravel()[tg], _oracle(b, tg))
+        print(f"autotune n={b.n} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+        assert e_rms <= 1e-5 and e_max <= 1e-4
+    plan.close()
+
+
+def test_schedule_validation():
+    lc = _lc()
+    box = _box(64, K=2)
+    plan = lc.Plan([box], precision=lc.LC_PREC_FP32)
+    s = plan.get_schedule(0)
+    for bad in (dict(xy_variant=s["n_xy"]), dict(xy_variant=-2), dict(fused_variant=s["n_fused"]),
+                dict(fused_rounds=2), dict(push_group=0), dict(push_group=65)):
+        with pytest.raises(lc.LCError) as ei:
+            plan.set_schedule(0, **bad)
+        assert ei.value.code == lc.LC_EINVAL
+    assert plan.get_schedule(0) == s
+    plan.close()
+    p64 = lc.Plan([box], precision=lc.LC_PREC_FP64)
+    s64 = p64.get_schedule(0)
+    assert s64["n_xy"] == 0 and s64["xy_variant"] == -1 and s64["fused_variant"] == -1
+    with pytest.raises(lc.LCError):
+        p64.set_schedule(0, xy_variant=0)
+    p64.close()
