@@ -89,6 +89,27 @@ struct FusedDev {
     int64_t tiles;
 };
 
+// Processing order of the main tiles in the rounds schedule. Main tile
+// q*NPB + pb covers columns p in [pb*CPW, (pb+1)*CPW) of row q (NPB tiles
+// per row); its kernel octant rows (folded q) are CPW floats, half a cache
+// line at CPW = 16. The tiles (q, pb), (q, pb^1), (q', pb), (q', pb^1),
+// with q' = N - q (and 0 <-> N/2), read the same octant lines. Workgroups
+// w, w+8, w+16, w+24 run on one XCD (workgroups are dispatched to the 8
+// XCDs in turn), so slot s of a block of 32 consecutive slots takes member
+// (s % 32) / 8 of group 8 * (s / 32) + s % 8: the four readers of a line
+// are resident together on one XCD and the line comes from its L2 once.
+// Other tile counts keep the identity order.
+__device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_tiles, int n, int npb) {
+    if (slot >= main_tiles || (npb & 1) || (main_tiles & 31)) return slot;
+    const int64_t blk = slot >> 5;
+    const int xcd = (int)(slot & 7), j = (int)((slot & 31) >> 3);
+    const int64_t g = blk * 8 + xcd;
+    const int half = npb / 2;
+    const int q = (int)(g / half), pb = 2 * (int)(g % half) + (j & 1);
+    const int row = j < 2 ? q : (q == 0 ? n / 2 : n - q);
+    return (int64_t)row * npb + pb;
+}
+
 template <int L, int NB_, typename S, int PF>
 __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
                                                                         const cx<float> *__restrict__ tw_g) {
@@ -161,49 +182,64 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 #pragma unroll
         for (int e = 0; e < E; ++e) gslot[e] = fold(EF::out_pos(t, e), L) * CPW + c;
 
+        // The slice loop runs to a multiple of PF with no branch in its body:
+        // slices past k1 read slice k1-1 again (valid, recently read memory)
+        // with kernel weight 0, which leaves the compensated sum's value
+        // unchanged. Branch-free, every wait for a load counts exactly the
+        // loads issued after it, so the prefetched slices stay in flight.
+        const int kend = k0 + (k1 - k0 + PF - 1) / PF * PF;
+        auto spec_at = [&](int k) {
+            return (const char *)(a.spec + (int64_t)(k < k1 ? k : k1 - 1) * a.spec_stride);
+        };
         // first-pass inputs of the next PF slices, kept in flight in a ring of
         // register buffers (PF slices of HBM latency hidden behind compute)
         cx<float> xb[PF][E];
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
-            if (k0 + j < k1) {
-                const char *src = (const char *)(a.spec + (int64_t)(k0 + j) * a.spec_stride);
+            const char *src = spec_at(k0 + j);
 #pragma unroll
-                for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
-            }
+            for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
         }
         // kernel octant rows of slice k are loaded one slice ahead into
         // registers and stored to LDS during slice k; a band without a kernel
-        // for slice k reads a valid octant with weight 0
-        float gn[NB_][GROWS];
+        // for slice k reads a valid octant with weight 0. The weight is
+        // applied at the LDS store, not at the load: arithmetic on the loaded
+        // values right away would wait for every load in flight before them,
+        // the prefetched slices included.
+        float gn[NB_][GROWS], gw[NB_];
         auto load_g = [&](int k) {
 #pragma unroll
             for (int b = 0; b < NB_; ++b) {
                 const int kc = b == 0 ? a.K0 : a.K1;
-                const int kb = k < kc ? k : 0;
-                const float wgt = k < kc ? 1.f : 0.f;
+                const bool on = k < kc && k < k1;
+                const int kb = on ? k : 0;
+                gw[b] = on ? 1.f : 0.f;
                 const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
 #pragma unroll
-                for (int j = 0; j < GROWS; ++j) gn[b][j] = wgt * *(const float *)(gp + goff[j]);
+                for (int j = 0; j < GROWS; ++j) gn[b][j] = *(const float *)(gp + goff[j]);
             }
         };
+        // octant rows of slice k go to LDS buffer k&1, whose previous
+        // contents (slice k-2) were last read before the barriers of slice k-1
+        auto store_g = [&](int k) {
+            float *glk = &gl[k & 1][0][0];
+#pragma unroll
+            for (int b = 0; b < NB_; ++b)
+#pragma unroll
+                for (int jj = 0; jj < GROWS; ++jj) {
+                    const int rf = t + jj * RSTEP;
+                    if (rf < HP) glk[b * HP * CPW + rf * CPW + c] = gw[b] * gn[b][jj];
+                }
+        };
         load_g(k0);
-        for (int kk = k0; kk < k1; kk += PF) {
+        store_g(k0);
+        for (int kk = k0; kk < kend; kk += PF) {
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
                 const int k = kk + j;
-                if (k >= k1) break;   // uniform across the workgroup
-                // the LDS buffer k&1 was last read during slice k-2, before the
-                // barriers of slice k-1
-                float *glk = &gl[k & 1][0][0];
-#pragma unroll
-                for (int b = 0; b < NB_; ++b)
-#pragma unroll
-                    for (int jj = 0; jj < GROWS; ++jj) {
-                        const int rf = t + jj * RSTEP;
-                        if (rf < HP) glk[b * HP * CPW + rf * CPW + c] = gn[b][jj];
-                    }
-                if (k + 1 < k1) load_g(k + 1);
+                const float *glk = &gl[k & 1][0][0];
+                // the next slice's octant rows are in flight during this slice
+                load_g(k + 1);
                 EF::first(xb[j], lds, c, ES, t);
                 cx<float> v[E];
                 if constexpr (EF::NP == 1) {
@@ -212,8 +248,8 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                     lds_barrier();    // kernel values in LDS visible
                 }
                 // buffer j is free: refill it with slice k + PF
-                if (k + PF < k1) {
-                    const char *src = (const char *)(a.spec + (int64_t)(k + PF) * a.spec_stride);
+                {
+                    const char *src = spec_at(k + PF);
 #pragma unroll
                     for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
                 }
@@ -231,6 +267,9 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                         sum[b][e].x = tx;
                         sum[b][e].y = ty;
                     }
+                // stored at the end of the slice, after the refill loads were
+                // issued, so that waiting for them does not wait for the refill
+                store_g(k + 1);
             }
         }
 
@@ -262,7 +301,10 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         };
     if (a.rounds) {
         // whole tiles in rounds: all workgroups sweep the slices together
-        for (int64_t tile = w; tile < a.tiles; tile += a.P) segment(tile, 0, a.kmax);
+        // main tiles per row (1: rows do not split into whole tiles, identity order)
+        const int npb = (L / 2) % CPW == 0 ? (int)((L / 2) / CPW) : 1;
+        for (int64_t slot = w; slot < a.tiles; slot += a.P)
+            segment(fused_slot_tile(slot, s0.n_wgs, L, npb), 0, a.kmax);
     } else {
         while (pos < end) {
             const int64_t tile = pos / a.kmax;

@@ -451,9 +451,14 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
     const int n = bp.n;
     const int64_t se = spec_elems(n);
     SrcTab tab;
+    // inputs: the spectrum memory of other slices, read as FP32 grids (a
+    // slice's spectrum is larger than a grid). With cnt > K/2 some inputs
+    // are also outputs of the same launch; the values are then meaningless
+    // but every access stays inside the spectrum store, and the run time
+    // does not depend on them.
     for (int j = 0; j < cnt; ++j)
-        tab.p[j] = bp.K >= 2 * cnt ? (const void *)(bp.spec + (size_t)((k0 + j + bp.K / 2) % bp.K) * se * 8)
-                                   : (const void *)p->scratch_real;
+        tab.p[j] = bp.K > 1 ? (const void *)(bp.spec + (size_t)((k0 + j + std::max(cnt, bp.K / 2)) % bp.K) * se * 8)
+                            : (const void *)p->scratch_real;
     char *out = bp.spec + (size_t)k0 * se * 8;
     double *dcp = bp.dcpart + (size_t)k0 * std::max(bp.n, bp.xwgs);
     if (xyv >= 0)
@@ -474,33 +479,23 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     const int reps = 3;
     double best = 1e30, ms = 0.0;
     int rot = 0;
-    // forward pass shape, per slice, at the default batching
+    // forward pass shape and slices per launch, jointly (per slice time)
     {
-        const int g = std::max(1, std::min(bp.push_group, bp.K / 2));
-        int bestv = -1;
-        for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v) {
-            int rc = time_calls(p->stream, reps, [&]() {
-                const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
-                return tune_forward(p, bp, v, g, k0);
-            }, &ms);
-            if (rc) return rc;
-            if (ms < best) { best = ms; bestv = v; }
-        }
+        std::vector<int> cands;
+        const int gmax = std::min(bp.K, SrcTab::kMax);
+        for (int g = 1; g < gmax; g *= 2) cands.push_back(g);
+        cands.push_back(gmax);   // all slices (up to the table size) in one launch
+        int bestv = -1, bestg = bp.push_group;
+        for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v)
+            for (int g : cands) {
+                int rc = time_calls(p->stream, reps, [&]() {
+                    const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
+                    return tune_forward(p, bp, v, g, k0);
+                }, &ms);
+                if (rc) return rc;
+                if (ms / g < best) { best = ms / g; bestv = v; bestg = g; }
+            }
         bp.xy_variant = bestv >= 0 ? bestv : 0;
-    }
-    // slices per forward launch
-    {
-        best = 1e30;
-        int bestg = bp.push_group;
-        for (int g = 1; g <= 16; g *= 2) {
-            if (g > std::max(1, bp.K / 2)) break;
-            int rc = time_calls(p->stream, reps, [&]() {
-                const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
-                return tune_forward(p, bp, bp.use_xy ? bp.xy_variant : -1, g, k0);
-            }, &ms);
-            if (rc) return rc;
-            if (ms / g < best) { best = ms / g; bestg = g; }
-        }
         bp.push_group = bestg;
     }
     // fused z pass schedule and scheduling mode (with the inverse y pass

@@ -29,6 +29,7 @@
 //
 // The FP64 sum of the input plane (the DC mode of Eq. 12, kept in FP64 for
 // the FP32 form) is written per plane to dcpart.
+#include <algorithm>
 #include <type_traits>
 
 #include "lc_fft_device.h"
@@ -94,16 +95,24 @@ __device__ __forceinline__ constexpr int partner_e(int e, bool t0) {
 __device__ __forceinline__ void pin(cx<float> &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
-template <int N, typename TIN, bool S8, int NB_, int NC_>
+template <int N, typename TIN, bool S8, int NB_, int NC_, bool PER>
 __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
     SrcTab srcs, cx<float> *__restrict__ spec0, int64_t spec_stride, const cx<float> *__restrict__ tw_half,
     const cx<float> *__restrict__ twist, const cx<float> *__restrict__ tw_full, double *__restrict__ dcpart,
-    int64_t dc_stride) {
+    int64_t dc_stride, int n_planes) {
     using SH = XYShape<N, S8, NB_, NC_>;
     constexpr int L = SH::L, TX = SH::TX, NB = SH::NB, RPB = SH::RPB, CPB = SH::CPB, NT = SH::NT;
     constexpr int SK = SH::SK, LSX = SH::LSX, ES = SH::ES, NC = SH::NC, XS = SH::XS, RG = SH::RG;
-    // row batches in flight ahead of the transform (FP64 input loads are twice as wide)
-    constexpr int PF = NB < 2 ? NB : (std::is_same<TIN, float>::value ? 2 : 1);
+    constexpr bool F32IN = std::is_same<TIN, float>::value;
+    static_assert(!PER || F32IN, "the persistent form reads FP32 grids");
+    // Row batches in flight ahead of their transform. One workgroup per
+    // plane: two batches (FP32 input) or one (FP64 input, whose loads are
+    // twice as wide). Persistent workgroups: the first half of the next
+    // plane is fetched during the last column batches of the current one's
+    // y phase, the second half half a plane ahead during its x phase (more
+    // would not fit in registers without spills, whose reloads would wait
+    // for the loads in flight).
+    constexpr int PF = PER ? (NB + 1) / 2 : (F32IN ? (NB < 2 ? NB : 2) : 1);
     using EX = Engine<float, L, true, typename SH::SX, SK>;
     using EY = Engine<float, N, true, typename SH::SY>;
     constexpr int EXN = EX::E, EYN = EY::E;
@@ -116,160 +125,211 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
-    const int slice = blockIdx.x / N, z = blockIdx.x % N;
-    const TIN *__restrict__ in = (const TIN *)srcs.p[slice] + (int64_t)z * N * N;
-    cx<float> *__restrict__ mainp = spec0 + slice * spec_stride + (int64_t)z * N * L;
-    cx<float> *__restrict__ nyq = spec0 + slice * spec_stride + spec_main(N) + (int64_t)z * N;
-
-    // ---- 1. rows of the plane (row batch b, row xl of the batch), read PF
-    //         batches ahead of their transform
     const int xl = tid / TX, xt = tid % TX;
-    cx<float> xr[NB][EXN];
-    double dsum = 0.0;
-    auto load_batch = [&](auto bc) {
+    const int yc = tid % CPB, yt = tid / CPB;
+    const int lane = tid & 63;
+    const int partner_lane = (lane & ~(TX - 1)) | ((TX - xt) & (TX - 1));
+    const bool t0 = xt == 0;
+    const int stride = gridDim.x;   // persistent form: planes w, w + stride, ... of workgroup w
+
+    // row batch b of plane `pl` (row xl of the batch) into dst[b]; with
+    // `late`, the address passes through an empty asm statement so that the
+    // loads stay after the preceding barrier instead of being hoisted to
+    // where their registers are still taken
+    auto load_batch = [&](auto bc, int pl, cx<float>(&dst)[NB][EXN], bool late) {
         constexpr int b = decltype(bc)::value;
         if constexpr (b < NB) {
-            const TIN *row = in + (int64_t)(b * RPB + xl) * N;
+            // (the offset, not the pointer, goes through the asm: the pointer
+            // keeps its global address space, so these stay global loads,
+            // which LDS waits do not wait for)
+            int64_t off = ((int64_t)(pl % N) * N + b * RPB + xl) * N;
+            if (late) asm volatile("" : "+v"(off));
+            const TIN *row = (const TIN *)srcs.p[pl / N] + off;
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
                 const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
-                xr[b][e] = mk((float)v.x, (float)v.y);
+                dst[b][e] = mk((float)v.x, (float)v.y);
             }
         }
     };
-    static_for<PF>(load_batch);
+
+    int plane = blockIdx.x;
+    cx<float> xr[NB][EXN];
+    static_for<PF>([&](auto bc) { load_batch(bc, plane, xr, false); });
     for (int i = tid; i < L; i += NT) {
         twx[i] = tw_half[i];
         twt[i] = twist[i];
     }
     for (int i = tid; i < N; i += NT) twy[i] = tw_full[i];
 
-    // ---- 2. x transforms and untangle, one row batch at a time
-    const int lane = tid & 63;
-    const int partner_lane = (lane & ~(TX - 1)) | ((TX - xt) & (TX - 1));
-    const bool t0 = xt == 0;
-    static_for<NB>([&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        load_batch(std::integral_constant<int, b + PF>{});
-        if constexpr (std::is_same<TIN, float>::value) {
-            // FP32 input converts exactly: sum it here, before the batch is
-            // transformed, so the raw values need not stay live
+    auto body = [&](int plane) {
+        const int slice = plane / N, z = plane % N;
+        cx<float> *__restrict__ mainp = spec0 + slice * spec_stride + (int64_t)z * N * L;
+        cx<float> *__restrict__ nyq = spec0 + slice * spec_stride + spec_main(N) + (int64_t)z * N;
+        const int next = plane + stride;
+        const bool has_next = PER && next < n_planes;
+        cx<float> xn[NB][EXN];   // the next plane's rows (persistent form)
+        double dsum = 0.0;
+
+        // ---- 2. x transforms and untangle, one row batch at a time
+        static_for<NB>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            load_batch(std::integral_constant<int, b + PF>{}, plane, xr, true);
+            if constexpr (F32IN) {
+                // FP32 input converts exactly: sum it here, before the batch is
+                // transformed, so the raw values need not stay live
 #pragma unroll
-            for (int e = 0; e < EXN; ++e) dsum += (double)xr[b][e].x + (double)xr[b][e].y;
-            pin(dsum);
-        }
-        EX::run(xr[b], lds, xl * LSX, 1, xt, twx);
-        cx<float> pv[EXN];
-#pragma unroll
-        for (int e = 0; e < EXN; ++e) {
-            const cx<float> s = xr[b][partner_e<RL, BPTL>(e, false)];
-            cx<float> o;
-            o.x = __shfl(s.x, partner_lane, 64);
-            o.y = __shfl(s.y, partner_lane, 64);
-            pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
-        }
-#pragma unroll
-        for (int e = 0; e < EXN; ++e) {
-            const int q = EX::out_pos(xt, e);
-            const cx<float> A = xr[b][e], B = pv[e];
-            const cx<float> Ev = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
-            const cx<float> O = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
-            if (e == 0 && t0) {
-                // q = 0: Y[0] = Re A + Im A and Y[L] = Re A - Im A, both real: packed
-                xr[b][e] = mk(A.x + A.y, A.x - A.y);
-            } else {
-                xr[b][e] = Ev + cmul(twt[q], O);
+                for (int e = 0; e < EXN; ++e) dsum += (double)xr[b][e].x + (double)xr[b][e].y;
+                pin(dsum);
             }
-            pin(xr[b][e]);
-        }
-        if constexpr (NC > 0) {
-            // elements of the first NC column batches go to their LDS regions now
-            const int row = b * RPB + xl;
+            EX::run(xr[b], lds, xl * LSX, 1, xt, twx);
+            cx<float> pv[EXN];
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
-                const int i = e / RL, r = e % RL;
-                const int cb = (r * M + i * TX) / CPB;
-                if (cb < NC) lds[XS + cb * RG + row * ES + (EX::out_pos(xt, e) - cb * CPB)] = xr[b][e];
+                const cx<float> sv = xr[b][partner_e<RL, BPTL>(e, false)];
+                cx<float> o;
+                o.x = __shfl(sv.x, partner_lane, 64);
+                o.y = __shfl(sv.y, partner_lane, 64);
+                pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
             }
-        }
-    });
-
-    // ---- 3. y transforms, one column batch at a time
-    const int yc = tid % CPB, yt = tid / CPB;
-    static_for<NB>([&](auto cbc) {
-        constexpr int cb = decltype(cbc)::value;
-        // transposed batch: its own region (filled by the x phase) or the scratch
-        cx<float> *reg = cb < NC ? lds + XS + cb * RG : lds;
-        if constexpr (cb >= NC) {
-            lds_barrier();   // earlier readers of the scratch are done
-            static_for<NB>([&](auto bc) {
-                constexpr int b = decltype(bc)::value;
+#pragma unroll
+            for (int e = 0; e < EXN; ++e) {
+                const int q = EX::out_pos(xt, e);
+                const cx<float> A = xr[b][e], B = pv[e];
+                const cx<float> Ev = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
+                const cx<float> O = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
+                if (e == 0 && t0) {
+                    // q = 0: Y[0] = Re A + Im A and Y[L] = Re A - Im A, both real: packed
+                    xr[b][e] = mk(A.x + A.y, A.x - A.y);
+                } else {
+                    xr[b][e] = Ev + cmul(twt[q], O);
+                }
+                pin(xr[b][e]);
+            }
+            if constexpr (NC > 0) {
+                // elements of the first NC column batches go to their LDS regions now
                 const int row = b * RPB + xl;
 #pragma unroll
                 for (int e = 0; e < EXN; ++e) {
                     const int i = e / RL, r = e % RL;
-                    if ((r * M + i * TX) / CPB == cb) {
-                        const int q = EX::out_pos(xt, e);
-                        reg[row * ES + (q - cb * CPB)] = xr[b][e];
-                    }
+                    const int cb = (r * M + i * TX) / CPB;
+                    if (cb < NC) lds[XS + cb * RG + row * ES + (EX::out_pos(xt, e) - cb * CPB)] = xr[b][e];
                 }
-            });
-        }
-        lds_barrier();
-        cx<float> y[EYN];
-#pragma unroll
-        for (int e = 0; e < EYN; ++e) y[e] = reg[EY::in_pos(yt, e) * ES + yc];
-        EY::run(y, reg, yc, ES, yt, twy);
-        const int p = cb * CPB + yc;
-        if (p != 0) {
-#pragma unroll
-            for (int e = 0; e < EYN; ++e) mainp[(int64_t)EY::out_pos(yt, e) * L + p] = y[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < EYN; ++e) zb[EY::out_pos(yt, e)] = y[e];
-        }
-    });
+            }
+        });
 
-    // ---- 4. separate the packed p = 0 / p = N/2 column; FP64 plane sum
-    if constexpr (!std::is_same<TIN, float>::value) {
-        // FP64 input: the sum needs the values before rounding; read them again
+        // ---- 3. y transforms, one column batch at a time
+        static_for<NB>([&](auto cbc) {
+            constexpr int cb = decltype(cbc)::value;
+            // transposed batch: its own region (filled by the x phase) or the scratch
+            cx<float> *reg = cb < NC ? lds + XS + cb * RG : lds;
+            if constexpr (cb >= NC) {
+                lds_barrier();   // earlier readers of the scratch are done
+                static_for<NB>([&](auto bc) {
+                    constexpr int b = decltype(bc)::value;
+                    const int row = b * RPB + xl;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const TIN *row = in + (int64_t)(b * RPB + xl) * N;
-            for (int e = 0; e < EXN; ++e) {
-                const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
-                dsum += (double)v.x + (double)v.y;
+                    for (int e = 0; e < EXN; ++e) {
+                        const int i = e / RL, r = e % RL;
+                        if ((r * M + i * TX) / CPB == cb) {
+                            const int q = EX::out_pos(xt, e);
+                            reg[row * ES + (q - cb * CPB)] = xr[b][e];
+                        }
+                    }
+                });
+            }
+            lds_barrier();
+            if constexpr (PER) {
+                // registers are freeing up: fetch a row batch of the next plane
+                if constexpr (cb >= NB - PF) {
+                    if (has_next) load_batch(std::integral_constant<int, cb - (NB - PF)>{}, next, xn, true);
+                }
+            }
+            cx<float> y[EYN];
+#pragma unroll
+            for (int e = 0; e < EYN; ++e) y[e] = reg[EY::in_pos(yt, e) * ES + yc];
+            EY::run(y, reg, yc, ES, yt, twy);
+            const int p = cb * CPB + yc;
+            if (p != 0) {
+#pragma unroll
+                for (int e = 0; e < EYN; ++e) mainp[(int64_t)EY::out_pos(yt, e) * L + p] = y[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < EYN; ++e) zb[EY::out_pos(yt, e)] = y[e];
+            }
+        });
+
+        // ---- 4. separate the packed p = 0 / p = N/2 column; FP64 plane sum
+        if constexpr (!F32IN) {
+            // FP64 input: the sum needs the values before rounding; read them again
+            const TIN *in = (const TIN *)srcs.p[slice] + (int64_t)z * N * N;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const TIN *row = in + (int64_t)(b * RPB + xl) * N;
+                for (int e = 0; e < EXN; ++e) {
+                    const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
+                    dsum += (double)v.x + (double)v.y;
+                }
             }
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
-    if (lane == 0) red[tid >> 6] = dsum;
-    lds_barrier();
-    for (int k = tid; k < N; k += NT) {
-        const cx<float> A = zb[k], B = zb[(N - k) % N];
-        mainp[(int64_t)k * L] = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
-        nyq[k] = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
-    }
-    if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += red[w];
-        dcpart[slice * dc_stride + z] = s;
+        for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
+        if (lane == 0) red[tid >> 6] = dsum;
+        lds_barrier();
+        for (int k = tid; k < N; k += NT) {
+            const cx<float> A = zb[k], B = zb[(N - k) % N];
+            mainp[(int64_t)k * L] = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
+            nyq[k] = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
+        }
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            dcpart[slice * dc_stride + z] = sum;
+        }
+        if constexpr (PER) {
+#pragma unroll
+            for (int b = 0; b < PF; ++b)
+#pragma unroll
+                for (int e = 0; e < EXN; ++e) xr[b][e] = xn[b][e];
+        }
+    };
+    if constexpr (PER) {
+        for (; plane < n_planes; plane += stride) body(plane);
+    } else {
+        body(plane);
     }
 }
 
 bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
 
 // Launch shapes compiled per N (schedule, batches); the plan picks one.
-int xy_variants(int n) { return n == 256 ? 3 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
+int xy_variants(int n) { return n == 256 ? 4 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
 
-template <int N, typename TIN, bool S8, int NB, int NC>
+template <int N, typename TIN, bool S8, int NB, int NC, bool PER>
 static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_stride, const void *tw_half,
                        const void *twist, const void *tw_full, double *dcpart, int64_t dc_stride,
                        hipStream_t st) {
     using SH = XYShape<N, S8, NB, NC>;
-    hipLaunchKernelGGL((xy_fwd_kernel<N, TIN, S8, NB, NC>), dim3((unsigned)(N * count)), dim3(SH::NT), 0, st, in,
+    const int n_planes = N * count;
+    int grid = n_planes;
+    if constexpr (PER) {
+        // one resident workgroup per slot; each walks planes w, w + grid, ...
+        static int slots = 0;
+        if (!slots) {
+            int dev = 0, per_cu = 0;
+            hipDeviceProp_t prop;
+            if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+                return hipErrorInvalidDevice;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, xy_fwd_kernel<N, TIN, S8, NB, NC, PER>,
+                                                             SH::NT, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            slots = per_cu * prop.multiProcessorCount;
+        }
+        grid = std::min(grid, slots);
+    }
+    hipLaunchKernelGGL((xy_fwd_kernel<N, TIN, S8, NB, NC, PER>), dim3((unsigned)grid), dim3(SH::NT), 0, st, in,
                        (cx<float> *)spec, spec_stride, (const cx<float> *)tw_half, (const cx<float> *)twist,
-                       (const cx<float> *)tw_full, dcpart, dc_stride);
+                       (const cx<float> *)tw_full, dcpart, dc_stride, n_planes);
     return hipGetLastError();
 }
 
@@ -279,24 +339,25 @@ hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, 
     if (count < 1 || count > SrcTab::kMax || !dcpart) return hipErrorInvalidValue;
     if (variant < 0 || variant >= xy_variants(n)) return hipErrorInvalidValue;
     if (in_f64) variant = 0;   // the FP64-input instances of the other shapes spill
-#define X_(N, S8, NB, NC)                                                                                      \
-    return in_f64 ? xy_t<N, double, S8, NB, NC>(in, count, spec, spec_stride, tw_half, twist, tw_full, dcpart, \
-                                                dc_stride, st)                                                 \
-                  : xy_t<N, float, S8, NB, NC>(in, count, spec, spec_stride, tw_half, twist, tw_full, dcpart,  \
-                                               dc_stride, st);
+#define X_(N, S8, NB, NC, PER)                                                                              \
+    return in_f64 ? xy_t<N, double, S8, NB, NC, false>(in, count, spec, spec_stride, tw_half, twist, tw_full, \
+                                                       dcpart, dc_stride, st)                                 \
+                  : xy_t<N, float, S8, NB, NC, PER>(in, count, spec, spec_stride, tw_half, twist, tw_full,    \
+                                                    dcpart, dc_stride, st);
     switch (n) {
-        case 64: X_(64, false, 1, 0)
-        case 96: X_(96, false, 1, 0)
+        case 64: X_(64, false, 1, 0, false)
+        case 96: X_(96, false, 1, 0, false)
         case 128:
-            if (variant == 0) { X_(128, false, 1, 0) }
-            X_(128, true, 2, 0)
+            if (variant == 0) { X_(128, false, 1, 0, false) }
+            X_(128, true, 2, 0, false)
         case 192:
-            if (variant == 0) { X_(192, false, 4, 3) }
-            X_(192, false, 4, 0)
+            if (variant == 0) { X_(192, false, 4, 3, false) }
+            X_(192, false, 4, 0, false)
         case 256:
-            if (variant == 0) { X_(256, true, 8, 3) }
-            if (variant == 1) { X_(256, false, 4, 1) }
-            X_(256, true, 4, 1)
+            if (variant == 0) { X_(256, true, 8, 3, false) }
+            if (variant == 1) { X_(256, false, 4, 1, false) }
+            if (variant == 2) { X_(256, true, 4, 1, false) }
+            X_(256, true, 8, 3, true)
         default: return hipErrorInvalidValue;
     }
 #undef X_
