@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "retarded-field cell-updates/s (cells×slices/s) + HBM GB/s vs peak; FP32 vs FP64"
-SRC_FILES = ["lc_fft_device.h", "lc_fft.hip", "lc_field.hip", "lc_greens.hip", "lc_host.cpp",
+SRC_FILES = ["lc_fft_device.h", "lc_fft.hip", "lc_xy.hip", "lc_field.hip", "lc_greens.hip", "lc_host.cpp",
              "lc_internal.h"]
 
 
@@ -111,9 +111,12 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
     res = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "build_s": t_build,
            "value": n ** 3 * K / (ms * 1e-3), "schedule": sched}
     if time_kernels:
+        group = 1
         if sched["xy_variant"] >= 0:
+            # timed in the step's launch configuration: `group` slices per launch
+            group = min(sched["push_group"], K)
             ids = {"xy_fwd": lc.LC_KERNEL_XY_FWD}
-            per_step = {"xy_fwd": K}
+            per_step = {"xy_fwd": K / group}
         else:
             ids = {"x_fwd": lc.LC_KERNEL_X_FWD, "col_y_fwd": lc.LC_KERNEL_COL_Y_FWD}
             per_step = {"x_fwd": K, "col_y_fwd": K}
@@ -128,11 +131,13 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
             per_step.update({"col_z_fwd": K, "mac": K * B, "col_z_inv": B})
         csz, rsz = (16, 8) if precision == lc.LC_PREC_FP64 else (8, 4)
         model = bytes_model(n, K, min(B, 2) if fused else B, fused, csz, rsz)
+        model["xy_fwd"] *= group
         kern = {}
         for name, kid in ids.items():
-            reps = 3 if name == "fused_z" else 2 * K
+            reps = 3 if name == "fused_z" else (2 * K if name != "xy_fwd" else max(3, 2 * K // group))
             t = plan.time_kernel(kid, 0, reps)
             kern[name] = {"avg_ms": t, "launches_per_step": per_step[name],
+                          "slices_per_launch": group if name == "xy_fwd" else 1,
                           "alg_bytes": model[name],
                           "GBps": model[name] / (t * 1e-3) / 1e9,
                           "step_share": t * per_step[name] / ms}
@@ -231,13 +236,17 @@ def main():
             tj = json.load(open(tpath))
             ent = tj.get(f"{w.name}:{dom}")
             if ent and ent.get("src_hash") == src_hash():
-                traffic = ent["bytes_per_launch"]
+                if "bytes_per_slice" in ent:   # kernels launched over several slices
+                    traffic = ent["bytes_per_slice"] * kd["slices_per_launch"]
+                else:
+                    traffic = ent["bytes_per_launch"]
         except Exception:
             traffic = None
     line["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": kd["GBps"], "peak": HBM_PEAK_GBPS,
                         "unit": "GB/s", "frac": kd["GBps"] / HBM_PEAK_GBPS, "traffic": traffic}
     line["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "GBps": round(v["GBps"], 1),
-                           "step_share": round(v["step_share"], 3)} for k, v in kern.items()}
+                           "step_share": round(v["step_share"], 3),
+                           "slices_per_launch": v["slices_per_launch"]} for k, v in kern.items()}
     alg_step = n ** 3 * K * 4 + (n // 2 + 1) ** 3 * K * 4 * len(box.bands)
     line["step_alg_GBps"] = alg_step / (r32["ms_per_step"] * 1e-3) / 1e9
     line["build_s"] = r32["build_s"]

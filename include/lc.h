@@ -249,7 +249,9 @@ int lc_set_schedule(lc_plan_t *plan, int32_t box, const lc_schedule *s);
  * HIP events recorded on that stream. Per-slice kernels cycle over the
  * box's slices; LC_KERNEL_X_FWD and LC_KERNEL_XY_FWD read the dense device
  * grid most recently pushed for the slice (a zeroed scratch grid if none);
- * per-band kernels
+ * LC_KERNEL_XY_FWD runs in the step's configuration, min(push_group, K)
+ * slices per launch (lc_schedule), and its time is per launch; per-band
+ * kernels
  * use band 0 (the fused pass handles bands 0-1); the output of
  * LC_KERNEL_X_INV goes to the workspace scratch. Kernels must be built.
  * The plan's spectra and accumulators are left unspecified: push every

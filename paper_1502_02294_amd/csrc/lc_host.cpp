@@ -1036,11 +1036,18 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                                     fused && !bp.use_xy ? bp.dcpart + (size_t)k * bp.dcw : nullptr, st);
             }
             case LC_KERNEL_XY_FWD: {
+                // the step's launch configuration: push_group slices per launch
+                const int g = std::min(bp.push_group, bp.K);
+                const int kg = ((rep - 1) * g) % (bp.K - g + 1);
                 SrcTab tab;
-                tab.p[0] = bp.last_src[k] ? bp.last_src[k] : p->scratch_real;
-                const bool in_f64 = bp.last_src[k] ? bp.last_src_f64[k] != 0 : false;
-                return launch_xy_fwd_batch(n, tab, 1, in_f64, speck, 0, bp.tw_half, bp.twist, bp.tw_full,
-                                           bp.dcpart + (size_t)k * bp.dcw, bp.dcw, bp.xy_variant, st);
+                bool in_f64 = false;
+                for (int j = 0; j < g; ++j) {
+                    tab.p[j] = bp.last_src[kg + j] ? bp.last_src[kg + j] : p->scratch_real;
+                    in_f64 = bp.last_src[kg + j] ? bp.last_src_f64[kg + j] != 0 : false;
+                }
+                return launch_xy_fwd_batch(n, tab, g, in_f64, bp.spec + (size_t)kg * se * cs, se, bp.tw_half,
+                                           bp.twist, bp.tw_full, bp.dcpart + (size_t)kg * bp.dcw, bp.dcw,
+                                           bp.xy_variant, st);
             }
             case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, speck, bp.tw_full, st);
             case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, speck, bp.tw_full, st);
