@@ -76,6 +76,28 @@ template <int N, bool S8, int NB_, int NC_> struct XYShape {
     static_assert(CPB % TX == 0, "column batches must hold whole lane groups of a row");
 };
 
+// Value held by lane (TX - t) mod TX of the same TX-lane group (the lane
+// of the untangle partner), moved with DPP instead of an LDS permute:
+//   TX = 4: quad permutation [0, 3, 2, 1];
+//   TX = 8 / 16: mirror within 8 / 16 lanes, then shift right by one lane.
+// Lanes t = 0 use their own registers instead and ignore the result (their
+// value crosses from the neighbouring group).
+template <int TX> __device__ __forceinline__ float partner_val(float v) {
+    const int iv = __float_as_int(v);
+    if constexpr (TX == 2) {
+        return v;   // lane 1 is its own partner
+    } else if constexpr (TX == 4) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(iv, 0 | (3 << 2) | (2 << 4) | (1 << 6), 0xF, 0xF, true));
+    } else if constexpr (TX == 8) {
+        const int m = __builtin_amdgcn_mov_dpp(iv, 0x141, 0xF, 0xF, true);    // row_half_mirror
+        return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x111, 0xF, 0xF, true));  // row_shr:1
+    } else {
+        static_assert(TX == 16, "untangle lane groups of 2, 4, 8 or 16 lanes");
+        const int m = __builtin_amdgcn_mov_dpp(iv, 0x140, 0xF, 0xF, true);    // row_mirror
+        return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x111, 0xF, 0xF, true));  // row_shr:1
+    }
+}
+
 // Element index, in the same thread or in lane TX - t, holding the partner
 // position L - q of the element e of the last x pass. Output positions of the
 // last pass are q = t + i*TX + r*M (e = i*RL + r, M = L/RL = BPT*TX).
@@ -128,7 +150,6 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
     const int xl = tid / TX, xt = tid % TX;
     const int yc = tid % CPB, yt = tid / CPB;
     const int lane = tid & 63;
-    const int partner_lane = (lane & ~(TX - 1)) | ((TX - xt) & (TX - 1));
     const bool t0 = xt == 0;
     const int stride = gridDim.x;   // persistent form: planes w, w + stride, ... of workgroup w
 
@@ -156,9 +177,11 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
     int plane = blockIdx.x;
     cx<float> xr[NB][EXN];
     static_for<PF>([&](auto bc) { load_batch(bc, plane, xr, false); });
+    // untangle twist as V_q = -i W^q / 2:  Y[q] = (A + conj B) / 2 + V_q (A - conj B)
     for (int i = tid; i < L; i += NT) {
         twx[i] = tw_half[i];
-        twt[i] = twist[i];
+        const cx<float> w = twist[i];
+        twt[i] = mk(0.5f * w.y, -0.5f * w.x);
     }
     for (int i = tid; i < N; i += NT) twy[i] = tw_full[i];
 
@@ -187,22 +210,20 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
                 const cx<float> sv = xr[b][partner_e<RL, BPTL>(e, false)];
-                cx<float> o;
-                o.x = __shfl(sv.x, partner_lane, 64);
-                o.y = __shfl(sv.y, partner_lane, 64);
+                const cx<float> o = mk(partner_val<TX>(sv.x), partner_val<TX>(sv.y));
                 pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
             }
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
                 const int q = EX::out_pos(xt, e);
                 const cx<float> A = xr[b][e], B = pv[e];
-                const cx<float> Ev = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
-                const cx<float> O = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
                 if (e == 0 && t0) {
                     // q = 0: Y[0] = Re A + Im A and Y[L] = Re A - Im A, both real: packed
                     xr[b][e] = mk(A.x + A.y, A.x - A.y);
                 } else {
-                    xr[b][e] = Ev + cmul(twt[q], O);
+                    const cx<float> S = mk(A.x + B.x, A.y - B.y), D = mk(A.x - B.x, A.y + B.y);
+                    const cx<float> V = twt[q];
+                    xr[b][e] = mk(fmaf(0.5f, S.x, V.x * D.x - V.y * D.y), fmaf(0.5f, S.y, V.x * D.y + V.y * D.x));
                 }
                 pin(xr[b][e]);
             }
