@@ -357,8 +357,8 @@ static hipError_t col_comb_t(void *spec, const void *tw, const int *tab, const v
     using SH = ColShape<float, N>;
     ColSet s0, s1;
     col_sets<float, N>(1, s0, s1);
-    // the fused pass tiles its N*H main columns by ColShape<float, N>::CPW
-    const int cpw_z = SH::CPW;
+    // the fused pass tiles its N*H main columns by fused_cpw(N) columns
+    const int cpw_z = fused_cpw(N);
     const int64_t tiles_main = ((int64_t)N * (N / 2) + cpw_z - 1) / cpw_z;
     hipLaunchKernelGGL((col_kernel<float, N, false, true>), dim3(s0.n_wgs + s1.n_wgs), dim3(SH::NT), 0, st,
                        (cx<float> *)spec, (int64_t)0, s0, s1, (const cx<float> *)tw, tab,

@@ -193,6 +193,7 @@ template <int L> struct Sched8;
 LC_SCHED8(64, 2, 8, 8, 0, 0, 8)
 LC_SCHED8(128, 3, 8, 2, 8, 0, 16)
 LC_SCHED8(256, 3, 8, 4, 8, 0, 32)
+LC_SCHED8(384, 4, 8, 3, 4, 4, 48)
 LC_SCHED8(512, 3, 8, 8, 8, 0, 64)
 #undef LC_SCHED8
 
@@ -424,7 +425,13 @@ template <typename T, int L> struct ColShape {
 // workgroup (128-byte rows).
 template <int L, typename S> struct FusedShape {
     static constexpr int TPL = S::TPL;
-    static constexpr int CPW = (16 * TPL >= 64) ? 16 : 64 / TPL;
+    // 16 columns (a 128-byte row segment), at most 512 threads (so that a
+    // thread keeps a 256-register budget; a power of two below that), at
+    // least one wave
+    static constexpr int CMAX = 512 / TPL < 16 ? 512 / TPL : 16;
+    static constexpr int CPW = (16 * TPL >= 64)
+                                   ? (CMAX >= 16 ? 16 : CMAX >= 8 ? 8 : CMAX >= 4 ? 4 : CMAX >= 2 ? 2 : 1)
+                                   : 64 / TPL;
     static constexpr int NT = CPW * TPL;
     static constexpr int PAD = 1;
     // requested waves per SIMD: bounds the register budget (512 / WPE)

@@ -10,6 +10,8 @@
 //                transform of each slice, the multiply by G^ and a
 //                compensated (Kahan) sum over slices are done in registers;
 //                the inverse z transform follows and A is written once.
+#include <type_traits>
+
 #include "lc_fft_device.h"
 #include "lc_internal.h"
 
@@ -331,9 +333,15 @@ __global__ __launch_bounds__(256) void fused_split_kernel(int *__restrict__ tab,
     tab[t] = v;
 }
 
+// Schedule that fixes the tiling of the fused pass for N: the 16-element
+// schedule, except at N = 384 and 512, where only the 8-element one keeps
+// its per-band compensated sums and prefetch ring in registers.
+template <int N> constexpr bool fused_sched8_only() { return N == 384 || N == 512; }
+template <int N> using FusedTiling = std::conditional_t<fused_sched8_only<N>(), Sched8<N>, Sched<N>>;
+
 template <int N>
 static void fused_sets(ColSet &s0, ColSet &s1) {
-    constexpr int CPW = FusedShape<N, Sched<N>>::CPW;
+    constexpr int CPW = FusedShape<N, FusedTiling<N>>::CPW;
     const int64_t H = N / 2;
     // main: columns (q, p) flat q*H + p; element (row r) at r*N*H + col
     s0.n_cols = (int64_t)N * H; s0.W = (int64_t)N * H; s0.plane_stride = 0; s0.col_stride = 1;
@@ -346,7 +354,9 @@ static void fused_sets(ColSet &s0, ColSet &s1) {
 }
 
 // variant 1: eight elements per thread (Sched8), where a schedule exists
-template <int N> struct HasSched8 { static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 512); };
+template <int N> struct HasSched8 {
+    static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 384 || N == 512);
+};
 
 template <int N, int NB, typename S, int PF>
 static int fused_slots() {
@@ -366,7 +376,7 @@ static int fused_slots() {
 template <int N, typename S, int PF>
 static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                                int64_t tiles, int kmax) {
-    static_assert(FusedShape<N, S>::CPW == FusedShape<N, Sched<N>>::CPW, "variants share the tiling");
+    static_assert(FusedShape<N, S>::CPW == FusedShape<N, FusedTiling<N>>::CPW, "variants share the tiling");
     const int slots = fa.nband == 2 ? fused_slots<N, 2, S, PF>() : fused_slots<N, 1, S, PF>();
     const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts);
     FusedDev d;
@@ -411,20 +421,34 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
                            (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, (int64_t)tiles);
         return hipGetLastError();
     }
-    // variant = 2 * schedule + (prefetch depth - 2); schedule 1 = Sched8
-    const int sched = fa.variant / 2, pf = 2 + fa.variant % 2;
+    // variant = 2 * schedule + (prefetch depth 1 ? 1 : 0); schedule 1 = Sched8
+    // (N = 512 compiles only the Sched8 pair)
+    const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 ? 1 : 2;
     if constexpr (HasSched8<N>::value) {
         if (sched == 1)
-            return pf == 3 ? fused_launch<N, Sched8<N>, 3>(fa, tw, st, s0, s1, tiles, kmax)
+            return pf == 1 ? fused_launch<N, Sched8<N>, 1>(fa, tw, st, s0, s1, tiles, kmax)
                            : fused_launch<N, Sched8<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
     }
-    return pf == 3 ? fused_launch<N, Sched<N>, 3>(fa, tw, st, s0, s1, tiles, kmax)
-                   : fused_launch<N, Sched<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
+    if constexpr (!fused_sched8_only<N>()) {
+        return pf == 1 ? fused_launch<N, Sched<N>, 1>(fa, tw, st, s0, s1, tiles, kmax)
+                       : fused_launch<N, Sched<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
+    }
+    return hipErrorInvalidValue;
 }
 
-// variants: bit 0 selects a prefetch depth of 3 (else 2) slices, bit 1 the
-// eight-element schedule where one exists
-int fused_variants(int n) { return (n == 64 || n == 128 || n == 256 || n == 512) ? 4 : 2; }
+// variants: bit 0 selects a prefetch depth of 1 (else 2) slices (fewer
+// registers: the two-band instances need it), bit 1 the eight-element
+// schedule where one exists (N = 384, 512: the eight-element schedule only,
+// bit 0 alone)
+int fused_variants(int n) { return (n == 384 || n == 512) ? 2 : (n == 64 || n == 128 || n == 256) ? 4 : 2; }
+
+// Built-in choice: prefetch depth 2 for one band per launch, 1 for two (the
+// two-band instances of depth 2 spill registers).
+int fused_default_variant(int n, int nband) {
+    if (n == 384) return 1;   // depth 1 is the instance without spills there
+    const int s8 = fused_variants(n) > 2 ? 2 : 0;
+    return s8 + (nband > 1 ? 1 : 0);
+}
 
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st) {
     if (a.nband < 1 || a.nband > 2) return hipErrorInvalidValue;
@@ -447,7 +471,7 @@ int64_t fused_tiles(int n) {
 
 int fused_cpw(int n) {
     switch (n) {
-#define X_(N) case N: return FusedShape<N, Sched<N>>::CPW;
+#define X_(N) case N: return FusedShape<N, FusedTiling<N>>::CPW;
         X_(8) X_(12) X_(16) X_(24) X_(32) X_(48) X_(64) X_(96) X_(128) X_(192) X_(256) X_(384) X_(512)
 #undef X_
         default: return 0;

@@ -584,7 +584,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             bp.max_parts = kMaxParts;
             bp.part_stride = kMaxParts * x.n * fused_cpw(x.n);
             bp.tiles = fused_tiles(x.n);
-            bp.fused_variant = fused_variants(x.n) > 2 ? 2 : 0;
+            bp.fused_variant = fused_default_variant(x.n, std::min(2, x.n_bands));
         } bp.maxima = (unsigned long long *)(p->ws + o.maxima);
         bp.tw_half = p->ws + o.tw_half; bp.tw_full = p->ws + o.tw_full; bp.twist = p->ws + o.twist;
         bp.tw64_half = p->ws + o.tw64_half; bp.tw64_full = p->ws + o.tw64_full;

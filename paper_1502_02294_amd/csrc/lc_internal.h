@@ -97,6 +97,7 @@ struct FusedArgs {
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
 };
 int fused_variants(int n);   // number of register schedules compiled for n
+int fused_default_variant(int n, int nband);   // built-in choice for 1 or 2 bands per launch
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);
 int64_t fused_tiles(int n);  // column tiles of the fused pass (main + nyq)
 int fused_cpw(int n);        // columns per tile

@@ -284,3 +284,27 @@ def test_time_kernel_reports_positive_durations():
     with pytest.raises(lc.LCError):
         plan.time_kernel(lc.LC_KERNEL_MAC, 0, 2)     # not part of the fused form
     plan.close()
+
+
+def test_grid384_sampled_fp64_and_fp32():
+    """N = 384 (radix 3 in every pass; eight-element fused schedule with
+    8-column tiles): two slices, sampled cells against route D."""
+    lc = _lc()
+    n, K = 384, 2
+    L = 0.78125 * n
+    radii = np.linspace(0.0, 0.12 * L, K + 1)
+    srcs = [li.random_sources([384, k], n, 300) for k in range(K)]
+    box = li.Box(n=n, box=L, radii=radii, supersample=2, bands=[li.Atten(kind=0)], sources=srcs)
+    tg = li.sample_cells([384, 1], n, 1500)
+    Jr = oracle.field_direct_ondemand(n, L, radii, 2, box.bands[0], srcs, tg)
+    for prec, tol in ((lc.LC_PREC_FP64, 1e-12), (lc.LC_PREC_FP32, 1e-5)):
+        print(f"case n=384 prec={prec}", flush=True)
+        plan = lc.Plan([box], precision=prec)
+        plan.build_all()
+        keep = [plan.push_points(0, k, torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
+                for k, (c, v) in enumerate(srcs)]
+        J = plan.field(0, 0).double().cpu().numpy().ravel()
+        plan.close()
+        e_max, e_rms = oracle.rel_errors(J[tg], Jr)
+        print(f"n=384 prec={prec} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+        assert (e_max if prec == lc.LC_PREC_FP64 else e_rms) <= tol
