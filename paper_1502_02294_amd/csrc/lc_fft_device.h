@@ -427,7 +427,8 @@ template <int L, typename S> struct FusedShape {
     static constexpr int TPL = S::TPL;
     // 16 columns (a 128-byte row segment), at most 512 threads (so that a
     // thread keeps a 256-register budget; a power of two below that), at
-    // least one wave
+    // least one wave. (8-column tiles at L = 256, two workgroups per CU,
+    // measured slower: half-line reads cost more than the overlap gains.)
     static constexpr int CMAX = 512 / TPL < 16 ? 512 / TPL : 16;
     static constexpr int CPW = (16 * TPL >= 64)
                                    ? (CMAX >= 16 ? 16 : CMAX >= 8 ? 8 : CMAX >= 4 ? 4 : CMAX >= 2 ? 2 : 1)

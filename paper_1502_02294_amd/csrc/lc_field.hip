@@ -93,23 +93,30 @@ struct FusedDev {
 
 // Processing order of the main tiles in the rounds schedule. Main tile
 // q*NPB + pb covers columns p in [pb*CPW, (pb+1)*CPW) of row q (NPB tiles
-// per row); its kernel octant rows (folded q) are CPW floats, half a cache
-// line at CPW = 16. The tiles (q, pb), (q, pb^1), (q', pb), (q', pb^1),
-// with q' = N - q (and 0 <-> N/2), read the same octant lines. Workgroups
-// w, w+8, w+16, w+24 run on one XCD (workgroups are dispatched to the 8
-// XCDs in turn), so slot s of a block of 32 consecutive slots takes member
-// (s % 32) / 8 of group 8 * (s / 32) + s % 8: the four readers of a line
-// are resident together on one XCD and the line comes from its L2 once.
-// Other tile counts keep the identity order.
-__device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_tiles, int n, int npb) {
-    if (slot >= main_tiles || (npb & 1) || (main_tiles & 31)) return slot;
-    const int64_t blk = slot >> 5;
-    const int xcd = (int)(slot & 7), j = (int)((slot & 31) >> 3);
+// per row). Its kernel octant rows (folded q) are CPW floats, so GP =
+// 32 / CPW neighbouring p-blocks share each 128-byte octant line, and the
+// rows q and q' = N - q (0 <-> N/2) fold to the same octant row: the 2*GP
+// tiles {q, q'} x {GP p-blocks} read the same octant lines (and, for
+// CPW < 16, the same spectrum lines). Workgroups w, w+8, w+16, ... run on
+// one XCD (workgroups are dispatched to the 8 XCDs in turn), so slot s of
+// a block of 16*GP consecutive slots takes member (s % (16 GP)) / 8 of
+// group 8 * (s / (16 GP)) + s % 8: the readers of a line are resident
+// together on one XCD and it comes from that XCD's L2 once. Other tile
+// counts, and tiles that do not split rows evenly (npb = 0), keep the
+// identity order; the result is always a main tile when slot is one.
+__device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_tiles, int n, int npb, int gp) {
+    const int bs = 16 * gp;
+    if (slot >= main_tiles || gp < 1 || npb < gp || npb % gp || main_tiles % bs ||
+        (int64_t)n * npb != main_tiles)
+        return slot;
+    const int64_t blk = slot / bs;
+    const int xcd = (int)(slot & 7), j = (int)((slot % bs) >> 3);
     const int64_t g = blk * 8 + xcd;
-    const int half = npb / 2;
-    const int q = (int)(g / half), pb = 2 * (int)(g % half) + (j & 1);
-    const int row = j < 2 ? q : (q == 0 ? n / 2 : n - q);
-    return (int64_t)row * npb + pb;
+    const int ngp = npb / gp;
+    const int q = (int)(g / ngp), pb = gp * (int)(g % ngp) + (j % gp);
+    const int row = j < gp ? q : (q == 0 ? n / 2 : n - q);
+    const int64_t tile = (int64_t)row * npb + pb;
+    return tile < main_tiles ? tile : slot;
 }
 
 template <int L, int NB_, typename S, int PF>
@@ -303,10 +310,11 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         };
     if (a.rounds) {
         // whole tiles in rounds: all workgroups sweep the slices together
-        // main tiles per row (1: rows do not split into whole tiles, identity order)
-        const int npb = (L / 2) % CPW == 0 ? (int)((L / 2) / CPW) : 1;
+        // main tiles per row (0: rows do not split into whole tiles, identity order)
+        const int npb = (L / 2) % CPW == 0 ? (int)((L / 2) / CPW) : 0;
+        constexpr int GP = CPW >= 32 ? 1 : 32 / CPW;
         for (int64_t slot = w; slot < a.tiles; slot += a.P)
-            segment(fused_slot_tile(slot, s0.n_wgs, L, npb), 0, a.kmax);
+            segment(fused_slot_tile(slot, s0.n_wgs, L, npb, GP), 0, a.kmax);
     } else {
         while (pos < end) {
             const int64_t tile = pos / a.kmax;
