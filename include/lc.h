@@ -219,19 +219,27 @@ typedef enum {
 /* Launch shapes of one box's tunable passes (a6: radix schedule, columns
  * per tile and LDS layout are compiled per shape; the plan picks one).
  *   xy_variant     fused forward x + y pass: shape in [0, n_xy), or -1 for
- *                  separate x and y passes (always -1 when n_xy = 0)
+ *                  separate x and y passes (always -1 when n_xy = 0). At
+ *                  N = 256, shapes 4..6 take half a z-plane (the rows of one
+ *                  parity) per workgroup and leave the y transforms of the
+ *                  even and the odd rows apart (parity layout); the fused z
+ *                  pass applies the last radix-2 step of the y transform.
  *   fused_variant  fused z pass register schedule in [0, n_fused)
  *                  (FP32 form; -1 in the other forms)
- *   fused_rounds   1: persistent workgroups take whole tiles in rounds;
- *                  0: the last round's tiles are split between two
- *                  workgroups and merged by the inverse y pass
+ *   fused_rounds   1: persistent workgroups take whole tiles in rounds; the
+ *                  tiles left over after the last whole round are split by
+ *                  slices over all workgroups and their parts merged by a
+ *                  small kernel. 0: all (tile, slice) pairs are split evenly
+ *                  between the workgroups; a tile's second part is merged by
+ *                  the inverse y pass
  *   push_group     slices per batched forward launch in lc_step, 1..64
  *   n_xy, n_fused  (lc_get_schedule only) shapes compiled for this N/form
  * lc_set_schedule validates every field (LC_EINVAL) and applies them to
  * later launches; the next lc_step captures a new graph. Changing whether
- * the fused xy pass is used clears the box's pushed slices (they read as
- * zero until pushed again). FP64 input grids (and point lists) always use
- * xy shape 0. */
+ * the fused xy pass is used, or between whole-plane and parity-layout
+ * shapes, clears the box's pushed slices (they read as zero until pushed
+ * again). FP64 input grids (and point lists) use the first shape of the
+ * same layout (0 or 4). */
 typedef struct {
     int32_t xy_variant;
     int32_t fused_variant;

@@ -10,6 +10,9 @@
 //                transform of each slice, the multiply by G^ and a
 //                compensated (Kahan) sum over slices are done in registers;
 //                the inverse z transform follows and A is written once.
+//                Slices left in the parity y layout by the half-plane xy
+//                pass get their last y radix-2 step on the way in, two
+//                output columns per input column.
 #include <type_traits>
 
 #include "lc_fft_device.h"
@@ -104,6 +107,9 @@ struct FusedDev {
 // together on one XCD and it comes from that XCD's L2 once. Other tile
 // counts, and tiles that do not split rows evenly (npb = 0), keep the
 // identity order; the result is always a main tile when slot is one.
+// With spectra in the parity layout, a tile covers rows q and q + N/2
+// (q < N/2) and the same pairing runs with N/2 in place of N: the octant
+// rows of tiles q and N/2 - q are {q, N/2 - q} for both.
 __device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_tiles, int n, int npb, int gp) {
     const int bs = 16 * gp;
     if (slot >= main_tiles || gp < 1 || npb < gp || npb % gp || main_tiles % bs ||
@@ -119,7 +125,16 @@ __device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_ti
     return tile < main_tiles ? tile : slot;
 }
 
-template <int L, int NB_, typename S, int PF>
+// PAR: the slice spectra are in the parity layout of the half-plane xy
+// shapes (rows r < N/2 of a z-plane hold the y transform E of the even rows,
+// rows N/2 + r that of the odd rows O). A column (q, p) with q < N/2 then
+// yields the two columns of rows q and q + N/2 of the length-N y transform,
+//   T[q] = E + W_N^q O,   T[q + N/2] = E - W_N^q O
+// (its last radix-2 step), formed on the way to the first butterfly: each
+// input element is read once for both, and both go through the z transform,
+// the kernel product and the compensated sum. Output o of a column is at
+// o * (N/2 rows) after the first; a second part goes to part slot 2 w + o.
+template <int L, int NB_, typename S, int PF, bool PAR>
 __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
                                                                         const cx<float> *__restrict__ tw_g) {
     using SH = FusedShape<L, S>;
@@ -130,11 +145,12 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     constexpr int HP = L / 2 + 1;
     constexpr int RSTEP = NT / CPW;                        // = threads per column
     constexpr int GROWS = (HP + RSTEP - 1) / RSTEP;        // octant rows loaded per thread
+    constexpr int NO = PAR ? 2 : 1;                        // output columns per input column
     __shared__ cx<float> lds[L * ES];
     __shared__ cx<float> tws[L];
-    // kernel octant rows of the tile (all folded z frequencies), double
-    // buffered by slice: rows r and L-r of a column share one entry
-    __shared__ float gl[2][NB_][HP * CPW];
+    // kernel octant rows of the tile (all folded z frequencies), per output,
+    // double buffered by slice: rows r and L-r of a column share one entry
+    __shared__ float gl[2][NB_ * NO][HP * CPW];
     for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
 
     const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
@@ -155,24 +171,34 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // columns past the end compute on a valid column and are not stored
         const int64_t ccol = col_ok ? col : col0;
         const int64_t cbase = col_base(s, ccol);
+        // row (y frequency) of the column; in the parity layout the second
+        // output and the O input are obase elements further
+        const int q = is_main ? (int)(ccol / H) : (int)ccol;
+        const int64_t obase = is_main ? (int64_t)H * H : (int64_t)H;
+        const cx<float> wq = tws[PAR ? q : 0];   // W_N^q
 
         // octant offset of this thread's column in one G^ slice; the row
-        // part (folded z frequency) is added per element
-        int gbase, grow;
+        // part (folded z frequency) is added per element. The second output
+        // (row q + N/2) is gdel floats further.
+        int gbase, grow, gdel = 0;
         if (is_main) {
             const int cc = (int)ccol;
-            gbase = fold(cc / H, L) * H + cc % H;
+            gbase = fold(q, L) * H + cc % H;
             grow = HP * H;
+            if constexpr (PAR) gdel = (fold(q + H, L) - fold(q, L)) * H;
         } else {
-            gbase = HP * HP * H + fold((int)ccol, L);
+            gbase = HP * HP * H + fold(q, L);
             grow = HP;
+            if constexpr (PAR) gdel = fold(q + H, L) - fold(q, L);
         }
 
-        cx<float> sum[NB_][E], cmp[NB_][E];
+        cx<float> sum[NO][NB_][E], cmp[NO][NB_][E];
 #pragma unroll
-        for (int b = 0; b < NB_; ++b)
+        for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int e = 0; e < E; ++e) { sum[b][e] = mk(0.f, 0.f); cmp[b][e] = mk(0.f, 0.f); }
+            for (int b = 0; b < NB_; ++b)
+#pragma unroll
+                for (int e = 0; e < E; ++e) { sum[o][b][e] = mk(0.f, 0.f); cmp[o][b][e] = mk(0.f, 0.f); }
 
         // byte offsets of this thread's inputs within one slice spectrum and
         // of the kernel octant rows it loads (rows t + j*RSTEP of its column),
@@ -201,21 +227,30 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
             return (const char *)(a.spec + (int64_t)(k < k1 ? k : k1 - 1) * a.spec_stride);
         };
         // first-pass inputs of the next PF slices, kept in flight in a ring of
-        // register buffers (PF slices of HBM latency hidden behind compute)
-        cx<float> xb[PF][E];
-#pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            const char *src = spec_at(k0 + j);
+        // register buffers (PF slices of HBM latency hidden behind compute);
+        // in the parity layout ob holds the O halves
+        constexpr int PO = PAR ? PF : 1;
+        cx<float> xb[PF][E], ob[PO][E];
+        const int64_t obytes = obase * 8;
+        auto fill = [&](int j, int k) {
+            const char *src = spec_at(k);
 #pragma unroll
             for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
-        }
+            if constexpr (PAR) {
+                const char *srco = src + obytes;
+#pragma unroll
+                for (int e = 0; e < E; ++e) ob[j][e] = *(const cx<float> *)(srco + xoff[e]);
+            }
+        };
+#pragma unroll
+        for (int j = 0; j < PF; ++j) fill(j, k0 + j);
         // kernel octant rows of slice k are loaded one slice ahead into
         // registers and stored to LDS during slice k; a band without a kernel
         // for slice k reads a valid octant with weight 0. The weight is
         // applied at the LDS store, not at the load: arithmetic on the loaded
         // values right away would wait for every load in flight before them,
         // the prefetched slices included.
-        float gn[NB_][GROWS], gw[NB_];
+        float gn[NB_][NO][GROWS], gw[NB_];
         auto load_g = [&](int k) {
 #pragma unroll
             for (int b = 0; b < NB_; ++b) {
@@ -225,7 +260,15 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 gw[b] = on ? 1.f : 0.f;
                 const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
 #pragma unroll
-                for (int j = 0; j < GROWS; ++j) gn[b][j] = *(const float *)(gp + goff[j]);
+                for (int o = 0; o < NO; ++o)
+#pragma unroll
+                    for (int j = 0; j < GROWS; ++j) {
+                        // the second output's rows are gdel floats away (gdel < 0
+                        // for q > N/4): the offset is formed in 32 bits, where it
+                        // wraps to the true (nonnegative) offset, before the add
+                        const uint32_t go = goff[j] + (uint32_t)(o * gdel) * 4u;
+                        gn[b][o][j] = *(const float *)(gp + go);
+                    }
             }
         };
         // octant rows of slice k go to LDS buffer k&1, whose previous
@@ -235,9 +278,26 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 #pragma unroll
             for (int b = 0; b < NB_; ++b)
 #pragma unroll
-                for (int jj = 0; jj < GROWS; ++jj) {
-                    const int rf = t + jj * RSTEP;
-                    if (rf < HP) glk[b * HP * CPW + rf * CPW + c] = gw[b] * gn[b][jj];
+                for (int o = 0; o < NO; ++o)
+#pragma unroll
+                    for (int jj = 0; jj < GROWS; ++jj) {
+                        const int rf = t + jj * RSTEP;
+                        if (rf < HP) glk[(b * NO + o) * HP * CPW + rf * CPW + c] = gw[b] * gn[b][o][jj];
+                    }
+        };
+        // compensated (Kahan) sum over slices of output o
+        auto mac = [&](int o, const float *glk, const cx<float>(&v)[E]) {
+#pragma unroll
+            for (int b = 0; b < NB_; ++b)
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const float gv = glk[(b * NO + o) * HP * CPW + gslot[e]];
+                    const float yx = gv * v[e].x - cmp[o][b][e].x, yy = gv * v[e].y - cmp[o][b][e].y;
+                    const float tx = sum[o][b][e].x + yx, ty = sum[o][b][e].y + yy;
+                    cmp[o][b][e].x = (tx - sum[o][b][e].x) - yx;
+                    cmp[o][b][e].y = (ty - sum[o][b][e].y) - yy;
+                    sum[o][b][e].x = tx;
+                    sum[o][b][e].y = ty;
                 }
         };
         load_g(k0);
@@ -249,6 +309,16 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 const float *glk = &gl[k & 1][0][0];
                 // the next slice's octant rows are in flight during this slice
                 load_g(k + 1);
+                if constexpr (PAR) {
+                    // last radix-2 step of the y transform: E +- W_N^q O
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const cx<float> x = xb[j][e], y = ob[j][e];
+                        const float ux = fmaf(wq.x, y.x, -wq.y * y.y), uy = fmaf(wq.x, y.y, wq.y * y.x);
+                        xb[j][e] = mk(x.x + ux, x.y + uy);
+                        ob[j][e] = mk(x.x - ux, x.y - uy);
+                    }
+                }
                 EF::first(xb[j], lds, c, ES, t);
                 cx<float> v[E];
                 if constexpr (EF::NP == 1) {
@@ -256,26 +326,21 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                     for (int e = 0; e < E; ++e) v[e] = xb[j][e];
                     lds_barrier();    // kernel values in LDS visible
                 }
-                // buffer j is free: refill it with slice k + PF
-                {
-                    const char *src = spec_at(k + PF);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
-                }
+                // buffer j is free (both halves once the second output has
+                // entered its transform): refill it with slice k + PF
+                if constexpr (!PAR) fill(j, k + PF);
                 if constexpr (EF::NP > 1) EF::rest(xb[j], v, lds, c, ES, t, tws);
-                // compensated (Kahan) sum over slices
+                mac(0, glk, v);
+                if constexpr (PAR) {
+                    EF::first(ob[j], lds, c, ES, t);   // (its barrier: readers of the first output are done)
+                    if constexpr (EF::NP == 1) {
 #pragma unroll
-                for (int b = 0; b < NB_; ++b)
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const float gv = glk[b * HP * CPW + gslot[e]];
-                        const float yx = gv * v[e].x - cmp[b][e].x, yy = gv * v[e].y - cmp[b][e].y;
-                        const float tx = sum[b][e].x + yx, ty = sum[b][e].y + yy;
-                        cmp[b][e].x = (tx - sum[b][e].x) - yx;
-                        cmp[b][e].y = (ty - sum[b][e].y) - yy;
-                        sum[b][e].x = tx;
-                        sum[b][e].y = ty;
+                        for (int e = 0; e < E; ++e) v[e] = ob[j][e];
                     }
+                    fill(j, k + PF);
+                    if constexpr (EF::NP > 1) EF::rest(ob[j], v, lds, c, ES, t, tws);
+                    mac(1, glk, v);
+                }
                 // stored at the end of the slice, after the refill loads were
                 // issued, so that waiting for them does not wait for the refill
                 store_g(k + 1);
@@ -286,35 +351,54 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         const bool has_dc = a.zero_dc && is_main && col == 0;
         const bool primary = k0 == 0;
 #pragma unroll
-        for (int b = 0; b < NB_; ++b) {
-            cx<float> y[E];
+        for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                y[e] = sum[b][e] - cmp[b][e];
-                if (has_dc && EF::out_pos(t, e) == 0) y[e] = mk(0.f, 0.f);
+            for (int b = 0; b < NB_; ++b) {
+                cx<float> y[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    y[e] = sum[o][b][e] - cmp[o][b][e];
+                    if (o == 0 && has_dc && EF::out_pos(t, e) == 0) y[e] = mk(0.f, 0.f);
+                }
+                // the last forward pass's placement is the first inverse pass's
+                EI::run(y, lds, c, ES, t, tws);
+                if (primary) {
+                    cx<float> *dst = a.acc + (int64_t)b * a.acc_stride + o * obase;
+                    if (col_ok)
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            dst[(uint32_t)(cbase + (int64_t)EI::out_pos(t, e) * s.row_stride)] = y[e];
+                } else {
+                    cx<float> *dst = a.part + (int64_t)b * a.part_stride + (int64_t)(NO * w + o) * (L * CPW) + c;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
+                }
             }
-            // the last forward pass's placement is the first inverse pass's
-            EI::run(y, lds, c, ES, t, tws);
-            if (primary) {
-                cx<float> *dst = a.acc + (int64_t)b * a.acc_stride;
-                if (col_ok)
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        dst[(uint32_t)(cbase + (int64_t)EI::out_pos(t, e) * s.row_stride)] = y[e];
-            } else {
-                cx<float> *dst = a.part + (int64_t)b * a.part_stride + (int64_t)w * (L * CPW) + c;
-#pragma unroll
-                for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
-            }
-        }
         };
     if (a.rounds) {
         // whole tiles in rounds: all workgroups sweep the slices together
         // main tiles per row (0: rows do not split into whole tiles, identity order)
         const int npb = (L / 2) % CPW == 0 ? (int)((L / 2) / CPW) : 0;
         constexpr int GP = CPW >= 32 ? 1 : 32 / CPW;
-        for (int64_t slot = w; slot < a.tiles; slot += a.P)
-            segment(fused_slot_tile(slot, s0.n_wgs, L, npb, GP), 0, a.kmax);
+        const int nrow = PAR ? L / 2 : L;
+        const int64_t full = a.tiles / a.P * a.P;   // slots of the whole rounds
+        for (int64_t slot = w; slot < full; slot += a.P)
+            segment(fused_slot_tile(slot, s0.n_wgs, nrow, npb, GP), 0, a.kmax);
+        // the tiles of the remaining slots (fewer than P) would leave most
+        // workgroups idle for a whole round: their (tile, slice) pairs are
+        // split evenly over all workgroups instead. Only a workgroup's first
+        // segment can start inside a tile; it goes to the workgroup's part
+        // slot, and fused_rest_merge_kernel adds the parts of each tile.
+        const int64_t U = (a.tiles - full) * a.kmax;
+        int64_t u = (int64_t)w * U / a.P;
+        const int64_t ue = (int64_t)(w + 1) * U / a.P;
+        while (u < ue) {
+            const int64_t i = u / a.kmax;
+            const int k0 = (int)(u % a.kmax);
+            const int k1 = (int)std::min<int64_t>(a.kmax, k0 + (ue - u));
+            u += k1 - k0;
+            segment(fused_slot_tile(full + i, s0.n_wgs, nrow, npb, GP), k0, k1);
+        }
     } else {
         while (pos < end) {
             const int64_t tile = pos / a.kmax;
@@ -326,9 +410,58 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     }
 }
 
-// tab[t] = the workgroup holding the second part of tile t, or -1
+// Parts of the tiles split by slices after the whole rounds (the rounds
+// schedule's remaining slots full .. full + rest - 1): slice unit u of those
+// tiles (u = i kmax + k for remaining tile i) belongs to workgroup w with
+// w U / P <= u < (w + 1) U / P, U = rest kmax. The workgroup whose range holds
+// unit i kmax wrote tile i to the accumulator; every other workgroup whose
+// range starts inside tile i left its part in slot NO w + o (output o). One
+// thread per (tile, output, band, element) adds them in workgroup order.
+struct RestMerge {
+    cx<float> *acc;
+    int64_t acc_stride;
+    const cx<float> *part;
+    int64_t part_stride;
+    int32_t nband, no, cpw, L;
+    int64_t full, rest, kmax, P;
+    int32_t npb, gp, nrow;
+};
+
+__global__ __launch_bounds__(256) void fused_rest_merge_kernel(RestMerge m, ColSet s0, ColSet s1) {
+    const int64_t per = (int64_t)m.L * m.cpw;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m.rest * m.no * m.nband * per) return;
+    const int64_t e = idx % per;
+    int64_t r = idx / per;
+    const int b = (int)(r % m.nband);
+    r /= m.nband;
+    const int o = (int)(r % m.no);
+    const int64_t i = r / m.no;
+    const int z = (int)(e / m.cpw), c = (int)(e % m.cpw);
+    const int64_t tile = fused_slot_tile(m.full + i, s0.n_wgs, m.nrow, m.npb, m.gp);
+    const bool is_main = tile < s0.n_wgs;
+    const ColSet &s = is_main ? s0 : s1;
+    const int64_t col = (is_main ? tile : tile - s0.n_wgs) * m.cpw + c;
+    if (col >= s.n_cols) return;
+    const int64_t H = m.L / 2;
+    const int64_t obase = is_main ? H * H : H;
+    const int64_t U = m.rest * m.kmax, lo = i * m.kmax, hi = lo + m.kmax;
+    cx<float> v = mk(0.f, 0.f);
+    // first workgroup whose range starts after unit lo: w U / P >= lo + 1
+    for (int64_t w = ((lo + 1) * m.P + U - 1) / U; w < m.P; ++w) {
+        const int64_t a0 = w * U / m.P, a1 = (w + 1) * U / m.P;
+        if (a0 >= hi) break;
+        if (a1 > a0) v = v + m.part[(int64_t)b * m.part_stride + (m.no * w + o) * per + e];
+    }
+    cx<float> *dst = m.acc + (int64_t)b * m.acc_stride + o * obase + col_base(s, col) + (int64_t)z * s.row_stride;
+    *dst = *dst + v;
+}
+
+// tab[t] = the workgroup holding the second part of tile t, or -1. With
+// two outputs per tile (parity layout: pair tiles, main_k of them main),
+// the entries go to the tiles of both output rows, as part slots 2 w + o.
 __global__ __launch_bounds__(256) void fused_split_kernel(int *__restrict__ tab, int64_t tiles, int64_t kmax,
-                                                          int64_t P, int64_t W) {
+                                                          int64_t P, int64_t W, int32_t pair, int64_t main_k) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= tiles) return;
     const int64_t lo = t * kmax;
@@ -338,7 +471,17 @@ __global__ __launch_bounds__(256) void fused_split_kernel(int *__restrict__ tab,
         const int64_t st = wc * W / P;
         if (st > lo && st < lo + kmax) v = (int)wc;
     }
-    tab[t] = v;
+    if (!pair) {
+        tab[t] = v;
+        return;
+    }
+    // standard tiles: main rows q < N/2 keep their index, rows q + N/2 are
+    // main_k further; nyq tiles follow the 2 main_k main ones, likewise
+    const int64_t nyq_k = tiles - main_k;
+    const int64_t t0 = t < main_k ? t : 2 * main_k + (t - main_k);
+    const int64_t t1 = t0 + (t < main_k ? main_k : nyq_k);
+    tab[t0] = v < 0 ? -1 : 2 * v;
+    tab[t1] = v < 0 ? -1 : 2 * v + 1;
 }
 
 // Schedule that fixes the tiling of the fused pass for N: the 16-element
@@ -347,15 +490,18 @@ __global__ __launch_bounds__(256) void fused_split_kernel(int *__restrict__ tab,
 template <int N> constexpr bool fused_sched8_only() { return N == 384 || N == 512; }
 template <int N> using FusedTiling = std::conditional_t<fused_sched8_only<N>(), Sched8<N>, Sched<N>>;
 
+// Column sets of the fused pass; with pair (parity layout) only the columns
+// of rows q < N/2, each standing for rows q and q + N/2.
 template <int N>
-static void fused_sets(ColSet &s0, ColSet &s1) {
+static void fused_sets(ColSet &s0, ColSet &s1, bool pair = false) {
     constexpr int CPW = FusedShape<N, FusedTiling<N>>::CPW;
     const int64_t H = N / 2;
+    const int64_t rows = pair ? H : N;
     // main: columns (q, p) flat q*H + p; element (row r) at r*N*H + col
-    s0.n_cols = (int64_t)N * H; s0.W = (int64_t)N * H; s0.plane_stride = 0; s0.col_stride = 1;
+    s0.n_cols = rows * H; s0.W = (int64_t)N * H; s0.plane_stride = 0; s0.col_stride = 1;
     s0.row_stride = (int64_t)N * H; s0.off = 0; s0.rowfast = 0;
     // nyq: columns q; element (row r) at main + r*N + q
-    s1.n_cols = N; s1.W = N; s1.plane_stride = 0; s1.col_stride = 1; s1.row_stride = N;
+    s1.n_cols = rows; s1.W = N; s1.plane_stride = 0; s1.col_stride = 1; s1.row_stride = N;
     s1.off = spec_main(N); s1.rowfast = 0;
     s0.n_wgs = (int32_t)((s0.n_cols + CPW - 1) / CPW);
     s1.n_wgs = (int32_t)((s1.n_cols + CPW - 1) / CPW);
@@ -366,27 +512,28 @@ template <int N> struct HasSched8 {
     static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 384 || N == 512);
 };
 
-template <int N, int NB, typename S, int PF>
+template <int N, int NB, typename S, int PF, bool PAR>
 static int fused_slots() {
     static int cached = 0;
     if (cached) return cached;
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S, PF>, FusedShape<N, S>::NT, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S, PF, PAR>, FusedShape<N, S>::NT,
+                                                     0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     cached = per_cu * prop.multiProcessorCount;
     return cached;
 }
 
-template <int N, typename S, int PF>
+template <int N, typename S, int PF, bool PAR>
 static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                                int64_t tiles, int kmax) {
     static_assert(FusedShape<N, S>::CPW == FusedShape<N, FusedTiling<N>>::CPW, "variants share the tiling");
-    const int slots = fa.nband == 2 ? fused_slots<N, 2, S, PF>() : fused_slots<N, 1, S, PF>();
-    const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts);
+    const int slots = fa.nband == 2 ? fused_slots<N, 2, S, PF, PAR>() : fused_slots<N, 1, S, PF, PAR>();
+    // (two part slots per workgroup with two outputs per tile)
+    const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts / (PAR ? 2 : 1));
     FusedDev d;
     d.spec = (const cx<float> *)fa.spec; d.spec_stride = fa.spec_stride;
     d.ghat = (const float *)fa.ghat; d.oct_stride = fa.oct_stride;
@@ -396,27 +543,69 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
     d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
     d.rounds = fa.rounds; d.tiles = tiles;
+    const int64_t std_tiles = PAR ? 2 * tiles : tiles;   // the table covers the tiles of every output row
     if (fa.rounds)   // no tile is split: every entry -1
-        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
-                           (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, tiles);
+        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((std_tiles + 255) / 256)), dim3(256), 0, st,
+                           (int *)fa.split_tab, std_tiles, (int64_t)1, (int64_t)1, std_tiles, 0, (int64_t)0);
     else
         hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
-                           (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W);
+                           (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W, PAR ? 1 : 0, (int64_t)s0.n_wgs);
     constexpr int NT = FusedShape<N, S>::NT;
     if (fa.nband == 2)
-        hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     else
-        hipLaunchKernelGGL((fused_z_kernel<N, 1, S, PF>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 1, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
+    const int64_t full = tiles / P * P;
+    if (fa.rounds && full < tiles) {
+        // parts of the tiles split by slices after the whole rounds
+        constexpr int CPW = FusedShape<N, S>::CPW;
+        RestMerge m;
+        m.acc = (cx<float> *)fa.acc; m.acc_stride = fa.acc_stride;
+        m.part = (const cx<float> *)fa.part; m.part_stride = fa.part_stride;
+        m.nband = fa.nband; m.no = PAR ? 2 : 1; m.cpw = CPW; m.L = N;
+        m.full = full; m.rest = tiles - full; m.kmax = kmax; m.P = P;
+        m.npb = (N / 2) % CPW == 0 ? (N / 2) / CPW : 0;
+        m.gp = CPW >= 32 ? 1 : 32 / CPW;
+        m.nrow = PAR ? N / 2 : N;
+        const int64_t threads = m.rest * m.no * m.nband * (int64_t)N * CPW;
+        hipLaunchKernelGGL(fused_rest_merge_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m,
+                           s0, s1);
+    }
     return hipGetLastError();
+}
+
+// parity-layout input: compiled where a half-plane xy shape exists (the
+// pair tiles need rows that split into whole tiles)
+template <int N> constexpr bool fused_par() { return N == 256; }
+static_assert((256 / 2) % FusedShape<256, FusedTiling<256>>::CPW == 0, "pair tiles cover whole rows");
+
+template <int N, bool PAR>
+static hipError_t fused_sched(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
+                              int64_t tiles, int kmax) {
+    // variant = 2 * schedule + (prefetch depth 1 ? 1 : 0); schedule 1 = Sched8
+    // (N = 384, 512 compile only the Sched8 pair)
+    const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 ? 1 : 2;
+    if constexpr (HasSched8<N>::value) {
+        if (sched == 1)
+            return pf == 1 ? fused_launch<N, Sched8<N>, 1, PAR>(fa, tw, st, s0, s1, tiles, kmax)
+                           : fused_launch<N, Sched8<N>, 2, PAR>(fa, tw, st, s0, s1, tiles, kmax);
+    }
+    if constexpr (!fused_sched8_only<N>()) {
+        return pf == 1 ? fused_launch<N, Sched<N>, 1, PAR>(fa, tw, st, s0, s1, tiles, kmax)
+                       : fused_launch<N, Sched<N>, 2, PAR>(fa, tw, st, s0, s1, tiles, kmax);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
+    if (fa.parity && !fused_par<N>()) return hipErrorInvalidValue;
     ColSet s0, s1;
-    fused_sets<N>(s0, s1);
+    fused_sets<N>(s0, s1, fa.parity != 0);
     const int64_t tiles = s0.n_wgs + s1.n_wgs;
+    const int64_t std_tiles = fa.parity ? 2 * tiles : tiles;
     const int kmax = std::max(fa.kcount[0], fa.nband > 1 ? fa.kcount[1] : 0);
     if (kmax <= 0) {
         // no slice contributes: the accumulators are zero
@@ -425,23 +614,14 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
                                              fa.acc_stride * 8, st);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
-                           (int *)fa.split_tab, tiles, (int64_t)1, (int64_t)1, (int64_t)tiles);
+        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((std_tiles + 255) / 256)), dim3(256), 0, st,
+                           (int *)fa.split_tab, std_tiles, (int64_t)1, (int64_t)1, std_tiles, 0, (int64_t)0);
         return hipGetLastError();
     }
-    // variant = 2 * schedule + (prefetch depth 1 ? 1 : 0); schedule 1 = Sched8
-    // (N = 512 compiles only the Sched8 pair)
-    const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 ? 1 : 2;
-    if constexpr (HasSched8<N>::value) {
-        if (sched == 1)
-            return pf == 1 ? fused_launch<N, Sched8<N>, 1>(fa, tw, st, s0, s1, tiles, kmax)
-                           : fused_launch<N, Sched8<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
+    if constexpr (fused_par<N>()) {
+        if (fa.parity) return fused_sched<N, true>(fa, tw, st, s0, s1, tiles, kmax);
     }
-    if constexpr (!fused_sched8_only<N>()) {
-        return pf == 1 ? fused_launch<N, Sched<N>, 1>(fa, tw, st, s0, s1, tiles, kmax)
-                       : fused_launch<N, Sched<N>, 2>(fa, tw, st, s0, s1, tiles, kmax);
-    }
-    return hipErrorInvalidValue;
+    return fused_sched<N, false>(fa, tw, st, s0, s1, tiles, kmax);
 }
 
 // variants: bit 0 selects a prefetch depth of 1 (else 2) slices (fewer
@@ -449,6 +629,8 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
 // schedule where one exists (N = 384, 512: the eight-element schedule only,
 // bit 0 alone)
 int fused_variants(int n) { return (n == 384 || n == 512) ? 2 : (n == 64 || n == 128 || n == 256) ? 4 : 2; }
+
+bool fused_parity_supported(int n) { return n == 256; }
 
 // Built-in choice: prefetch depth 2 for one band per launch, 1 for two (the
 // two-band instances of depth 2 spill registers).

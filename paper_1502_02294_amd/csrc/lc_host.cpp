@@ -237,7 +237,11 @@ struct BoxPlan {
     int xwgs = 0;
     // FP32 form at N in {64, 96, 128, 192, 256}: x and y passes fused per plane
     bool use_xy = false;
-    int dcw = 0;                 // FP64 DC partials per slice (x-pass workgroups or planes)
+    int dcw = 0;                 // FP64 DC partials per slice (x-pass workgroups, planes or half planes)
+    // spectra in the parity y layout (half-plane xy shapes), completed by the fused z pass
+    bool parity() const { return use_xy && xy_parity(n, xy_variant); }
+    int dc_width() const { return use_xy ? (parity() ? 2 : 1) * n : xwgs; }
+    int64_t dc_cap() const { return std::max<int64_t>(2 * (int64_t)n, xwgs); }   // dcpart entries per slice
 };
 
 struct lc_plan_s {
@@ -326,7 +330,7 @@ Layout layout_of(const lc_plan_desc *d) {
         o.acc = take((size_t)B * spec_elems(n) * cs);
         o.ghat = take((size_t)K * B * oct_elems(n) * rs);
         o.ghat0 = take((size_t)K * B * 8);
-        o.dcpart = take((size_t)K * std::max(x_pass_wgs(n), n) * 8);
+        o.dcpart = take((size_t)K * std::max(x_pass_wgs(n), 2 * n) * 8);
         o.mu = take((size_t)B * 8);
         o.sk = take((size_t)K * 8);
         if (d->precision == LC_PREC_FP32) {
@@ -440,6 +444,7 @@ FusedArgs fused_args(const BoxPlan &bp) {
     fa.split_tab = bp.split_tab;
     fa.variant = bp.fused_variant;
     fa.rounds = bp.fused_rounds;
+    fa.parity = bp.parity() ? 1 : 0;
     return fa;
 }
 
@@ -460,10 +465,10 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
         tab.p[j] = bp.K > 1 ? (const void *)(bp.spec + (size_t)((k0 + j + std::max(cnt, bp.K / 2)) % bp.K) * se * 8)
                             : (const void *)p->scratch_real;
     char *out = bp.spec + (size_t)k0 * se * 8;
-    double *dcp = bp.dcpart + (size_t)k0 * std::max(bp.n, bp.xwgs);
+    double *dcp = bp.dcpart + (size_t)k0 * bp.dc_cap();
     if (xyv >= 0)
-        return launch_xy_fwd_batch(n, tab, cnt, false, out, se, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.n, xyv,
-                                   p->stream);
+        return launch_xy_fwd_batch(n, tab, cnt, false, out, se, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.dc_cap(),
+                                   xyv, p->stream);
     hipError_t e = launch_x_fwd_batch(n, false, tab, cnt, false, out, se, bp.tw_half, bp.twist, dcp, p->stream);
     if (e != hipSuccess) return e;
     return launch_col_batch(n, false, 1, true, out, se, cnt, bp.tw_full, p->stream);
@@ -472,56 +477,71 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
 // Plan-time choice of the launch shapes of one FP32-form box (a6): every
 // compiled shape of the forward pass, the batching of the forward launches
 // and the fused z pass schedule is timed on this plan's buffers (all zero
-// at this point; the kernels' run time does not depend on the values) and
-// the fastest is kept. Spectra and DC partials are cleared afterwards.
+// at this point; the kernels' run time does not depend on the values).
+// The forward shapes come in two spectrum layouts (whole planes, or the
+// parity layout of the half-plane shapes, which the fused z pass completes
+// at some cost), so the fastest forward shape and fused schedule are found
+// per layout and the layout with the least K * (forward time per slice) +
+// (fused pass time) is kept. Spectra and DC partials are cleared afterwards.
 int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     const int n = bp.n;
     const int reps = 3;
-    double best = 1e30, ms = 0.0;
+    double ms = 0.0;
     int rot = 0;
-    // forward pass shape and slices per launch, jointly (per slice time)
+    // forward pass shape and slices per launch, jointly (per slice time), per layout
+    double fwd_best[2] = {1e30, 1e30};
+    int fwd_v[2] = {-1, -1}, fwd_g[2] = {bp.push_group, bp.push_group};
+    bool fwd_seen[2] = {false, false};
     {
         std::vector<int> cands;
         const int gmax = std::min(bp.K, SrcTab::kMax);
         for (int g = 1; g < gmax; g *= 2) cands.push_back(g);
         cands.push_back(gmax);   // all slices (up to the table size) in one launch
-        int bestv = -1, bestg = bp.push_group;
-        for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v)
+        for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v) {
+            const int lay = v >= 0 && xy_parity(n, v) ? 1 : 0;
+            if (lay == 1 && !fused_parity_supported(n)) continue;
             for (int g : cands) {
                 int rc = time_calls(p->stream, reps, [&]() {
                     const int k0 = (rot++ * g) % std::max(1, bp.K - g + 1);
                     return tune_forward(p, bp, v, g, k0);
                 }, &ms);
                 if (rc) return rc;
-                if (ms / g < best) { best = ms / g; bestv = v; bestg = g; }
+                fwd_seen[lay] = true;
+                if (ms / g < fwd_best[lay]) { fwd_best[lay] = ms / g; fwd_v[lay] = v; fwd_g[lay] = g; }
             }
-        bp.xy_variant = bestv >= 0 ? bestv : 0;
-        bp.push_group = bestg;
+        }
     }
     // fused z pass schedule and scheduling mode (with the inverse y pass
-    // that merges split tiles)
-    {
-        best = 1e30;
-        int bestv = bp.fused_variant, bestr = bp.fused_rounds;
+    // that merges split tiles), per layout
+    double fz_best[2] = {1e30, 1e30};
+    int fz_v[2] = {bp.fused_variant, bp.fused_variant}, fz_r[2] = {bp.fused_rounds, bp.fused_rounds};
+    for (int lay = 0; lay < 2; ++lay) {
+        if (!fwd_seen[lay]) continue;
         for (int v = 0; v < fused_variants(n); ++v)
             for (int r = 1; r >= 0; --r) {
                 bp.fused_variant = v;
                 bp.fused_rounds = r;
-                const FusedArgs fa = fused_args(bp);
+                FusedArgs fa = fused_args(bp);
+                fa.parity = lay;
                 int rc = time_calls(p->stream, 2, [&]() {
                     hipError_t e = launch_fused_z(n, fa, bp.tw_full, p->stream);
                     if (e != hipSuccess) return e;
                     return launch_col_y_inv_combine(n, bp.acc, bp.tw_full, bp.split_tab, bp.part, p->stream);
                 }, &ms);
                 if (rc) return rc;
-                if (ms < best) { best = ms; bestv = v; bestr = r; }
+                if (ms < fz_best[lay]) { fz_best[lay] = ms; fz_v[lay] = v; fz_r[lay] = r; }
             }
-        bp.fused_variant = bestv;
-        bp.fused_rounds = bestr;
     }
+    const int lay = fwd_seen[1] && (!fwd_seen[0] || bp.K * fwd_best[1] + fz_best[1] < bp.K * fwd_best[0] + fz_best[0])
+                        ? 1 : 0;
+    bp.xy_variant = fwd_v[lay] >= 0 ? fwd_v[lay] : 0;
+    bp.push_group = fwd_g[lay];
+    bp.fused_variant = fz_v[lay];
+    bp.fused_rounds = fz_r[lay];
+    bp.dcw = bp.dc_width();
     const size_t cs = 8;
     HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
-    HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
+    HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.dc_cap(), 0.0, p->stream));
     return LC_OK;
 }
 
@@ -591,7 +611,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         bp.twist64 = p->ws + o.twist64;
         bp.xwgs = x_pass_wgs(bp.n);
         bp.use_xy = p->prec == LC_PREC_FP32 && xy_supported(bp.n);
-        bp.dcw = bp.use_xy ? bp.n : bp.xwgs;
+        bp.dcw = bp.dc_width();
 
         // tables
         const int n = bp.n;
@@ -623,7 +643,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         }
         // slices never pushed are zero
         HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
-        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
+        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.dc_cap(), 0.0, p->stream));
         HIPCHK(launch_fill_f64(bp.ghat0, (int64_t)bp.K * bp.B, 0.0, p->stream));
         p->boxes.push_back(std::move(bp));
     }
@@ -639,6 +659,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
                 bp.push_group = done_bp[j]->push_group;
                 bp.fused_variant = done_bp[j]->fused_variant;
                 bp.fused_rounds = done_bp[j]->fused_rounds;
+                bp.dcw = bp.dc_width();
                 continue;
             }
             if ((rc = autotune_box(p.get(), bp))) return rc;
@@ -805,6 +826,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
             fa.split_tab = tab;
             fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
+            fa.parity = bp.parity() ? 1 : 0;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
                 char *acc = bp.acc + (size_t)(b + j) * se * cs;
@@ -1061,6 +1083,7 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                 fa.split_tab = bp.split_tab;
                 fa.variant = bp.fused_variant;
                 fa.rounds = bp.fused_rounds;
+                fa.parity = bp.parity() ? 1 : 0;
                 return launch_fused_z(n, fa, bp.tw_full, st);
             }
             case LC_KERNEL_MAC:
@@ -1119,17 +1142,19 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     if (s->push_group < 1 || s->push_group > SrcTab::kMax)
         return fail(LC_EINVAL, "push_group must be in [1, %d]", SrcTab::kMax);
     const bool use_xy = s->xy_variant >= 0;
-    if (use_xy != bp.use_xy) {
-        // the DC partial layout changes with the forward pass: pushed slices are dropped
-        bp.use_xy = use_xy;
-        bp.dcw = use_xy ? bp.n : bp.xwgs;
+    const bool par = use_xy && xy_parity(bp.n, s->xy_variant);
+    if (use_xy != bp.use_xy || par != bp.parity()) {
+        // the spectrum and DC partial layouts change with the forward pass:
+        // pushed slices are dropped
         const size_t cs = p->t_f64 ? 16 : 8;
         HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(bp.n) * cs, p->stream));
-        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * std::max(bp.n, bp.xwgs), 0.0, p->stream));
+        HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.dc_cap(), 0.0, p->stream));
         std::fill(bp.pushed.begin(), bp.pushed.end(), 0);
         std::fill(bp.last_src.begin(), bp.last_src.end(), nullptr);
     }
+    bp.use_xy = use_xy;
     if (use_xy) bp.xy_variant = s->xy_variant;
+    bp.dcw = bp.dc_width();
     if (fused) bp.fused_variant = s->fused_variant;
     bp.fused_rounds = s->fused_rounds;
     bp.push_group = s->push_group;

@@ -43,9 +43,17 @@ hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bo
 // writes its y-transformed spectrum at spec + i*spec_stride and one FP64 sum
 // of the input per plane at dcpart + i*dc_stride + z.
 // `variant` selects one of xy_variants(n) compiled launch shapes (FP64
-// input always runs shape 0).
+// input runs the first shape of the same layout).
+// Parity-layout shapes (xy_parity) take half a plane per workgroup, the rows y of one
+// parity s (y = 2m + s): rows r < N/2 of every z-plane of the spectrum then
+// hold the N/2-point y transform E of the even rows and rows N/2 + r that
+// of the odd rows O, so that the length-N y transform is
+//   T[q] = E[q mod N/2] + W_N^q O[q mod N/2]
+// (completed by the fused z pass, FusedArgs::parity), and the plane sums go
+// to dcpart + i*dc_stride + 2z + s (2N per slice).
 bool xy_supported(int n);
 int xy_variants(int n);
+bool xy_parity(int n, int variant);
 hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
                                const void *tw_half, const void *twist, const void *tw_full, double *dcpart,
                                int64_t dc_stride, int variant, hipStream_t st);
@@ -95,8 +103,10 @@ struct FusedArgs {
     int32_t kahan;           // 1: compensated sum
     int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
+    int32_t parity;          // 1: spectra in the parity y layout of the half-plane xy shapes
 };
 int fused_variants(int n);   // number of register schedules compiled for n
+bool fused_parity_supported(int n);   // parity-layout input compiled for n
 int fused_default_variant(int n, int nband);   // built-in choice for 1 or 2 bands per launch
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);
 int64_t fused_tiles(int n);  // column tiles of the fused pass (main + nyq)

@@ -7,6 +7,13 @@
 // y-transformed half spectrum once. Against separate x and y passes this
 // removes one full write and one full read of the spectrum per slice.
 //
+// The half-plane shapes (N = 256) give each workgroup the rows of one parity
+// instead, so that two workgroups share a CU and one computes while the
+// other waits for memory. Their y transforms have length N/2 and the slice
+// spectrum is left in the parity layout (even-row and odd-row transforms in
+// the lower and upper halves of every z-plane); the fused z pass applies the
+// last radix-2 step of the y transform.
+//
 //   1. Every row is read (all row batches issued up front) as N/2 complex
 //      values z[n] = x[2n] + i x[2n+1] and transformed by the N/2-point
 //      register-in/register-out engine, RPB rows at a time.
@@ -51,14 +58,19 @@ template <int C, int I = 0, typename F> __device__ __forceinline__ void static_f
 // register working set, one more LDS exchange per line), NB_ the number of
 // row batches of the x phase (= column batches of the y phase), NC_ the
 // number of column batches that the x phase deposits straight into LDS
-// regions of their own (the rest of the plane waits in registers).
-template <int N, bool S8, int NB_, int NC_> struct XYShape {
+// regions of their own (the rest of the plane waits in registers). NR_ is
+// the number of rows a workgroup takes (= the y transform length): N for a
+// whole plane, N/2 for the rows of one parity (y = 2m + s), whose y
+// transform leaves the last radix-2 step of the length-N one to the reader.
+template <int N, bool S8, int NB_, int NC_, int NR_ = N> struct XYShape {
     static constexpr int L = N / 2;
+    static constexpr int NR = NR_;
+    static constexpr int HALVES = N / NR;
     using SX = std::conditional_t<S8, Sched8<L>, Sched<L>>;
-    using SY = std::conditional_t<S8, Sched8<N>, Sched<N>>;
+    using SY = std::conditional_t<S8, Sched8<NR>, Sched<NR>>;
     static constexpr int TX = SX::TPL, TY = SY::TPL;
     static constexpr int NB = NB_;
-    static constexpr int RPB = N / NB;            // rows per x batch
+    static constexpr int RPB = NR / NB;           // rows per x batch
     static constexpr int CPB = L / NB;            // complex columns per y batch
     static constexpr int NT = TX * RPB;
     static constexpr int SK = 4;                  // x lines: one pad slot every 16 elements
@@ -66,11 +78,12 @@ template <int N, bool S8, int NB_, int NC_> struct XYShape {
     static constexpr int ES = CPB + 1;            // y: LDS row stride of the transposed batch
     static constexpr int NC = NC_;
     static constexpr int LDS_X = RPB * LSX;
-    static constexpr int RG = N * ES;                     // one transposed column batch
+    static constexpr int RG = NR * ES;                    // one transposed column batch
     static constexpr int XS = LDS_X > RG ? LDS_X : RG;    // x scratch, then y batches >= NC
     static constexpr int LDS = XS + NC * RG;
     static_assert(NC >= 0 && NC <= NB, "column batches held in LDS");
-    static_assert((LDS + 2 * L + 2 * N) * 8 + NT / 8 <= 160 * 1024, "LDS of one workgroup");
+    static_assert(HALVES == 1 || HALVES == 2, "whole planes or rows of one parity");
+    static_assert((LDS + 2 * L + 2 * NR) * 8 + NT / 8 <= 160 * 1024, "LDS of one workgroup");
     static_assert(NT == TY * CPB, "x and y phases must use the same thread count");
     static_assert(NT % 64 == 0 && NT <= 1024, "whole waves, one workgroup");
     static_assert(CPB % TX == 0, "column batches must hold whole lane groups of a row");
@@ -117,13 +130,14 @@ __device__ __forceinline__ constexpr int partner_e(int e, bool t0) {
 __device__ __forceinline__ void pin(cx<float> &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
-template <int N, typename TIN, bool S8, int NB_, int NC_, bool PER>
-__global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
+template <int N, int NR_, typename TIN, bool S8, int NB_, int NC_, bool PER>
+__global__ __launch_bounds__((XYShape<N, S8, NB_, NC_, NR_>::NT)) void xy_fwd_kernel(
     SrcTab srcs, cx<float> *__restrict__ spec0, int64_t spec_stride, const cx<float> *__restrict__ tw_half,
     const cx<float> *__restrict__ twist, const cx<float> *__restrict__ tw_full, double *__restrict__ dcpart,
     int64_t dc_stride, int n_planes) {
-    using SH = XYShape<N, S8, NB_, NC_>;
+    using SH = XYShape<N, S8, NB_, NC_, NR_>;
     constexpr int L = SH::L, TX = SH::TX, NB = SH::NB, RPB = SH::RPB, CPB = SH::CPB, NT = SH::NT;
+    constexpr int NR = SH::NR, HALVES = SH::HALVES;
     constexpr int SK = SH::SK, LSX = SH::LSX, ES = SH::ES, NC = SH::NC, XS = SH::XS, RG = SH::RG;
     constexpr bool F32IN = std::is_same<TIN, float>::value;
     static_assert(!PER || F32IN, "the persistent form reads FP32 grids");
@@ -136,14 +150,14 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
     // for the loads in flight).
     constexpr int PF = PER ? (NB + 1) / 2 : (F32IN ? (NB < 2 ? NB : 2) : 1);
     using EX = Engine<float, L, true, typename SH::SX, SK>;
-    using EY = Engine<float, N, true, typename SH::SY>;
+    using EY = Engine<float, NR, true, typename SH::SY>;
     constexpr int EXN = EX::E, EYN = EY::E;
     constexpr int RL = EX::RL, BPTL = EX::PLs::BPT, M = L / RL;
     static_assert(BPTL * TX == M, "last x pass layout");
 
     __shared__ cx<float> lds[SH::LDS];
-    __shared__ cx<float> twx[L], twt[L], twy[N];
-    __shared__ cx<float> zb[N];
+    __shared__ cx<float> twx[L], twt[L], twy[NR];
+    __shared__ cx<float> zb[NR];
     __shared__ double red[NT / 64];
 
     const int tid = threadIdx.x;
@@ -163,9 +177,10 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
             // (the offset, not the pointer, goes through the asm: the pointer
             // keeps its global address space, so these stay global loads,
             // which LDS waits do not wait for)
-            int64_t off = ((int64_t)(pl % N) * N + b * RPB + xl) * N;
+            const int pr = pl % (N * HALVES);   // (z, parity) of plane unit pl
+            int64_t off = ((int64_t)(pr / HALVES) * N + HALVES * (b * RPB + xl) + pr % HALVES) * N;
             if (late) asm volatile("" : "+v"(off));
-            const TIN *row = (const TIN *)srcs.p[pl / N] + off;
+            const TIN *row = (const TIN *)srcs.p[pl / (N * HALVES)] + off;
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
                 const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
@@ -183,12 +198,14 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
         const cx<float> w = twist[i];
         twt[i] = mk(0.5f * w.y, -0.5f * w.x);
     }
-    for (int i = tid; i < N; i += NT) twy[i] = tw_full[i];
+    for (int i = tid; i < NR; i += NT) twy[i] = tw_full[HALVES * i];   // W_NR^i = W_N^(HALVES i)
 
     auto body = [&](int plane) {
-        const int slice = plane / N, z = plane % N;
-        cx<float> *__restrict__ mainp = spec0 + slice * spec_stride + (int64_t)z * N * L;
-        cx<float> *__restrict__ nyq = spec0 + slice * spec_stride + spec_main(N) + (int64_t)z * N;
+        // plane unit: slice, z-plane and row parity (rows y = HALVES m + par);
+        // its y-transformed rows go to rows par*NR .. par*NR + NR-1
+        const int slice = plane / (N * HALVES), z = (plane % (N * HALVES)) / HALVES, par = plane % HALVES;
+        cx<float> *__restrict__ mainp = spec0 + slice * spec_stride + ((int64_t)z * N + par * NR) * L;
+        cx<float> *__restrict__ nyq = spec0 + slice * spec_stride + spec_main(N) + (int64_t)z * N + par * NR;
         const int next = plane + stride;
         const bool has_next = PER && next < n_planes;
         cx<float> xn[NB][EXN];   // the next plane's rows (persistent form)
@@ -286,7 +303,7 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
             const TIN *in = (const TIN *)srcs.p[slice] + (int64_t)z * N * N;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const TIN *row = in + (int64_t)(b * RPB + xl) * N;
+                const TIN *row = in + (int64_t)(HALVES * (b * RPB + xl) + par) * N;
                 for (int e = 0; e < EXN; ++e) {
                     const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
                     dsum += (double)v.x + (double)v.y;
@@ -296,15 +313,15 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
         for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
         if (lane == 0) red[tid >> 6] = dsum;
         lds_barrier();
-        for (int k = tid; k < N; k += NT) {
-            const cx<float> A = zb[k], B = zb[(N - k) % N];
+        for (int k = tid; k < NR; k += NT) {
+            const cx<float> A = zb[k], B = zb[(NR - k) % NR];
             mainp[(int64_t)k * L] = mk((A.x + B.x) * 0.5f, (A.y - B.y) * 0.5f);
             nyq[k] = mk((A.y + B.y) * 0.5f, (B.x - A.x) * 0.5f);
         }
         if (tid == 0) {
             double sum = 0.0;
             for (int w = 0; w < NT / 64; ++w) sum += red[w];
-            dcpart[slice * dc_stride + z] = sum;
+            dcpart[slice * dc_stride + z * HALVES + par] = sum;
         }
         if constexpr (PER) {
 #pragma unroll
@@ -323,14 +340,18 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_>::NT)) void xy_fwd_kernel(
 bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
 
 // Launch shapes compiled per N (schedule, batches); the plan picks one.
-int xy_variants(int n) { return n == 256 ? 4 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
+// At N = 256, shapes 4..6 take the rows of one parity per workgroup (half a
+// plane: two workgroups fit on a CU) and leave the spectrum in the parity
+// layout that the fused z pass completes.
+int xy_variants(int n) { return n == 256 ? 7 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
+bool xy_parity(int n, int variant) { return n == 256 && variant >= 4 && variant < 7; }
 
-template <int N, typename TIN, bool S8, int NB, int NC, bool PER>
+template <int N, int NR, typename TIN, bool S8, int NB, int NC, bool PER>
 static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_stride, const void *tw_half,
                        const void *twist, const void *tw_full, double *dcpart, int64_t dc_stride,
                        hipStream_t st) {
-    using SH = XYShape<N, S8, NB, NC>;
-    const int n_planes = N * count;
+    using SH = XYShape<N, S8, NB, NC, NR>;
+    const int n_planes = N * (N / NR) * count;
     int grid = n_planes;
     if constexpr (PER) {
         // one resident workgroup per slot; each walks planes w, w + grid, ...
@@ -340,7 +361,7 @@ static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_str
             hipDeviceProp_t prop;
             if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
                 return hipErrorInvalidDevice;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, xy_fwd_kernel<N, TIN, S8, NB, NC, PER>,
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, xy_fwd_kernel<N, NR, TIN, S8, NB, NC, PER>,
                                                              SH::NT, 0) != hipSuccess ||
                 per_cu < 1)
                 per_cu = 1;
@@ -348,7 +369,7 @@ static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_str
         }
         grid = std::min(grid, slots);
     }
-    hipLaunchKernelGGL((xy_fwd_kernel<N, TIN, S8, NB, NC, PER>), dim3((unsigned)grid), dim3(SH::NT), 0, st, in,
+    hipLaunchKernelGGL((xy_fwd_kernel<N, NR, TIN, S8, NB, NC, PER>), dim3((unsigned)grid), dim3(SH::NT), 0, st, in,
                        (cx<float> *)spec, spec_stride, (const cx<float> *)tw_half, (const cx<float> *)twist,
                        (const cx<float> *)tw_full, dcpart, dc_stride, n_planes);
     return hipGetLastError();
@@ -359,12 +380,16 @@ hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, 
                                int64_t dc_stride, int variant, hipStream_t st) {
     if (count < 1 || count > SrcTab::kMax || !dcpart) return hipErrorInvalidValue;
     if (variant < 0 || variant >= xy_variants(n)) return hipErrorInvalidValue;
-    if (in_f64) variant = 0;   // the FP64-input instances of the other shapes spill
-#define X_(N, S8, NB, NC, PER)                                                                              \
-    return in_f64 ? xy_t<N, double, S8, NB, NC, false>(in, count, spec, spec_stride, tw_half, twist, tw_full, \
-                                                       dcpart, dc_stride, st)                                 \
-                  : xy_t<N, float, S8, NB, NC, PER>(in, count, spec, spec_stride, tw_half, twist, tw_full,    \
-                                                    dcpart, dc_stride, st);
+    // FP64 input takes the first shape of the same spectrum layout (the
+    // FP64-input instances of the other shapes spill)
+    if (in_f64) variant = xy_parity(n, variant) ? 4 : 0;
+#define XS_(N, NR, S8, NB, NC, PER)                                                                            \
+    return in_f64 ? xy_t<N, NR, double, S8, NB, NC, false>(in, count, spec, spec_stride, tw_half, twist,       \
+                                                           tw_full, dcpart, dc_stride, st)                        \
+                  : xy_t<N, NR, float, S8, NB, NC, PER>(in, count, spec, spec_stride, tw_half, twist, tw_full,    \
+                                                        dcpart, dc_stride, st);
+#define X_(N, S8, NB, NC, PER) XS_(N, N, S8, NB, NC, PER)
+#define XH_(N, S8, NB, NC) XS_(N, N / 2, S8, NB, NC, false)
     switch (n) {
         case 64: X_(64, false, 1, 0, false)
         case 96: X_(96, false, 1, 0, false)
@@ -378,10 +403,15 @@ hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, 
             if (variant == 0) { X_(256, true, 8, 3, false) }
             if (variant == 1) { X_(256, false, 4, 1, false) }
             if (variant == 2) { X_(256, true, 4, 1, false) }
-            X_(256, true, 8, 3, true)
+            if (variant == 3) { X_(256, true, 8, 3, true) }
+            if (variant == 4) { XH_(256, false, 4, 1) }
+            if (variant == 5) { XH_(256, true, 8, 1) }
+            XH_(256, false, 4, 0)
         default: return hipErrorInvalidValue;
     }
+#undef XH_
 #undef X_
+#undef XS_
 }
 
 }  // namespace lc

@@ -87,6 +87,45 @@ def test_every_xy_shape_against_oracle(n):
     plan.close()
 
 
+@pytest.mark.parametrize("nbands", [1, 2])
+def test_parity_layout_every_fused_schedule(nbands):
+    """The half-plane xy shapes leave the y transforms of the even and the odd
+    rows apart (T[q] = E[q mod N/2] + W_N^q O[q mod N/2], Sec. 2.2's FFT
+    route with the last radix-2 step of the y transform deferred); the fused
+    z pass completes them. Every register schedule, both scheduling modes,
+    one and two bands per launch, against the oracle on sampled cells."""
+    lc = _lc()
+    n, K = 256, 3
+    box = _box(n, K=K, seed=31 + nbands)
+    L = box.box
+    if nbands == 2:
+        box.bands = [li.lw_band(0.3 * L), li.lw_band(0.15 * L)]
+    tg = _targets(n)
+    Jr = [oracle.field_direct_ondemand(n, L, box.radii, box.supersample, at, box.sources, tg)
+          for at in box.bands]
+    plan = lc.Plan([box], precision=lc.LC_PREC_FP32)
+    plan.build_all()
+    sch = plan.get_schedule(0)
+    par = [v for v in range(sch["n_xy"]) if v >= 4]
+    assert par, "N = 256 compiles half-plane xy shapes"
+    for xv in par:
+        plan.set_schedule(0, xy_variant=xv)
+        keep = [plan.push_grid(0, k, torch.from_numpy(li.dense_grid(n, cells, lum, np.float32)).cuda())
+                for k, (cells, lum) in enumerate(box.sources)]
+        torch.cuda.synchronize()
+        del keep
+        for fv in range(sch["n_fused"]):
+            for r in (1, 0):
+                print(f"case parity nbands={nbands} xy={xv} fused={fv} rounds={r}", flush=True)
+                plan.set_schedule(0, xy_variant=xv, fused_variant=fv, fused_rounds=r)
+                for b in range(nbands):
+                    J = plan.field(0, b).double().cpu().numpy().ravel()
+                    e_max, e_rms = oracle.rel_errors(J[tg], Jr[b])
+                    print(f"  band={b} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+                    assert e_rms <= 1e-5 and e_max <= 1e-4
+    plan.close()
+
+
 def test_xy_batched_step_and_empty_planes():
     """lc_step groups slices into one xy launch; an all-zero slice and a
     slice whose sources sit in one z-plane exercise the per-plane DC sums."""
