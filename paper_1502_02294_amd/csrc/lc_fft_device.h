@@ -285,6 +285,25 @@ __device__ __forceinline__ void run_passes(cx<T> *lds, int lbase, int es, int t,
     }
 }
 
+// Passes P .. PEND-1 with the exchanges alternating between two LDS line
+// buffers: exchange e (pass e + 1 reads, e = 0 written by the first pass)
+// uses buffer e % 2. A buffer written here was last read two exchanges
+// earlier, before the barrier that followed the exchange in between, so only
+// the barrier after each write (readers wait for writers) remains.
+template <typename T, int L, bool FWD, int P, int PEND, typename S, int SK>
+__device__ __forceinline__ void run_passes_db(cx<T> *la, cx<T> *lb, int lbase, int es, int t, const cx<T> *tw) {
+    if constexpr (P < PEND) {
+        constexpr int R = pass_radix<L, FWD, S>(P);
+        constexpr int NS = ns_before<L, FWD, S>(P);
+        using PS = Pass<T, L, R, NS, S::TPL, FWD, SK>;
+        cx<T> v[PS::BPT][R];
+        PS::read(((P - 1) & 1) ? lb : la, lbase, es, t, tw, v);
+        PS::write((P & 1) ? lb : la, lbase, es, t, v);
+        lds_barrier();
+        run_passes_db<T, L, FWD, P + 1, PEND, S, SK>(la, lb, lbase, es, t, tw);
+    }
+}
+
 // Register-in / register-out transform of one line by TPL threads.
 // x[e] (e < E) holds, on entry, the first pass's inputs at line positions
 // in_pos(t, e) and, on return, the last pass's outputs at out_pos(t, e).
@@ -343,6 +362,54 @@ struct Engine {
         first(x, lds, lbase, es, t);
         cx<T> y[E];
         rest(x, y, lds, lbase, es, t, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = y[e];
+    }
+
+    // The same transform with its exchanges alternating between the line
+    // buffers la and lb (run_passes_db). For a sequence of such transforms
+    // by the same threads (any mix of directions with this pass count) the
+    // barrier that protects earlier readers is needed only at the start of a
+    // transform whose predecessor's last exchange used la, i.e. when the
+    // number of exchanges NP - 1 is odd; the caller keeps other LDS users
+    // apart as before.
+    __device__ __forceinline__ static void first_db(cx<T> (&x)[E], cx<T> *la, int lbase, int es, int t) {
+#pragma unroll
+        for (int i = 0; i < P0::BPT; ++i) dft<R0, FWD>(x + i * R0);
+        if constexpr (NP > 1) {
+            if constexpr ((NP - 1) % 2 == 1) lds_barrier();
+#pragma unroll
+            for (int i = 0; i < P0::BPT; ++i) {
+                const int o = (t + i * TPL) * R0;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) la[lbase + lpos<SK>(o + r) * es] = x[i * R0 + r];
+            }
+        }
+    }
+    __device__ __forceinline__ static void rest_db(const cx<T> (&x)[E], cx<T> (&y)[E], cx<T> *la, cx<T> *lb,
+                                                   int lbase, int es, int t, const cx<T> *tw) {
+        if constexpr (NP == 1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = x[e];
+        } else {
+            lds_barrier();
+            run_passes_db<T, L, FWD, 1, NP - 1, S, SK>(la, lb, lbase, es, t, tw);
+            const cx<T> *src = ((NP - 2) & 1) ? lb : la;
+#pragma unroll
+            for (int i = 0; i < PLs::BPT; ++i) {
+                const int b = t + i * TPL;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) y[i * RL + r] = src[lbase + lpos<SK>(b + r * PLs::NB) * es];
+                PLs::twiddle(y + i * RL, b, tw);
+                dft<RL, FWD>(y + i * RL);
+            }
+        }
+    }
+    __device__ __forceinline__ static void run_db(cx<T> (&x)[E], cx<T> *la, cx<T> *lb, int lbase, int es,
+                                                  int t, const cx<T> *tw) {
+        first_db(x, la, lbase, es, t);
+        cx<T> y[E];
+        rest_db(x, y, la, lb, lbase, es, t, tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = y[e];
     }

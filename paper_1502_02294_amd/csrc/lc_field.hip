@@ -146,7 +146,9 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     constexpr int RSTEP = NT / CPW;                        // = threads per column
     constexpr int GROWS = (HP + RSTEP - 1) / RSTEP;        // octant rows loaded per thread
     constexpr int NO = PAR ? 2 : 1;                        // output columns per input column
-    __shared__ cx<float> lds[L * ES];
+    // z transform line buffers, alternated by exchange (Engine::run_db):
+    // only the barriers after the writes remain in the slice loop
+    __shared__ cx<float> lds[L * ES], lds2[L * ES];
     __shared__ cx<float> tws[L];
     // kernel octant rows of the tile (all folded z frequencies), per output,
     // double buffered by slice: rows r and L-r of a column share one entry
@@ -200,18 +202,23 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 #pragma unroll
                 for (int e = 0; e < E; ++e) { sum[o][b][e] = mk(0.f, 0.f); cmp[o][b][e] = mk(0.f, 0.f); }
 
-        // byte offsets of this thread's inputs within one slice spectrum and
-        // of the kernel octant rows it loads (rows t + j*RSTEP of its column),
-        // off workgroup-uniform bases (a slice spectrum is below 4 GiB)
-        uint32_t xoff[E], goff[GROWS];
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            xoff[e] = (uint32_t)((cbase + (int64_t)EF::in_pos(t, e) * s.row_stride) * 8);
-#pragma unroll
-        for (int j = 0; j < GROWS; ++j) {
-            const int rf = t + j * RSTEP;
-            goff[j] = (uint32_t)((gbase + (rf < HP ? rf : 0) * grow) * 4);
-        }
+        // Byte offsets, off workgroup-uniform bases (a slice spectrum is below
+        // 4 GiB): of this thread's first input element, the others being whole
+        // rows further (compile-time row deltas, folded into the uniform base),
+        // and of the kernel octant rows it loads (rows t + j*RSTEP of its
+        // column: uniform deltas too, except the last row, which is clamped
+        // for the threads past the octant's end). One offset register each
+        // instead of one per element.
+        const uint32_t xoff0 = (uint32_t)((cbase + (int64_t)EF::in_pos(t, 0) * s.row_stride) * 8);
+        const int64_t rs8 = s.row_stride * 8;
+        auto xld = [&](const char *base, int e) {
+            return *(const cx<float> *)(base + (int64_t)(EF::in_pos(t, e) - EF::in_pos(t, 0)) * rs8 + xoff0);
+        };
+        constexpr bool GFULL = GROWS * RSTEP <= HP;   // every thread's last row exists
+        const int rlast = t + (GROWS - 1) * RSTEP;
+        const uint32_t goff0 = (uint32_t)((gbase + t * grow) * 4);
+        const uint32_t goffl = (uint32_t)((gbase + (rlast < HP ? rlast : 0) * grow) * 4);
+        const int64_t gr4 = (int64_t)grow * 4 * RSTEP;
         // LDS slot of each output element's kernel value (folded row)
         int gslot[E];
 #pragma unroll
@@ -235,11 +242,11 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         auto fill = [&](int j, int k) {
             const char *src = spec_at(k);
 #pragma unroll
-            for (int e = 0; e < E; ++e) xb[j][e] = *(const cx<float> *)(src + xoff[e]);
+            for (int e = 0; e < E; ++e) xb[j][e] = xld(src, e);
             if constexpr (PAR) {
                 const char *srco = src + obytes;
 #pragma unroll
-                for (int e = 0; e < E; ++e) ob[j][e] = *(const cx<float> *)(srco + xoff[e]);
+                for (int e = 0; e < E; ++e) ob[j][e] = xld(srco, e);
             }
         };
 #pragma unroll
@@ -260,15 +267,17 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 gw[b] = on ? 1.f : 0.f;
                 const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
 #pragma unroll
-                for (int o = 0; o < NO; ++o)
+                for (int o = 0; o < NO; ++o) {
+                    // the second output's rows are gdel floats away (gdel < 0
+                    // for q > N/4): the offset is formed in 32 bits, where it
+                    // wraps to the true (nonnegative) offset, before the add
+                    const uint32_t od = (uint32_t)(o * gdel) * 4u;
 #pragma unroll
-                    for (int j = 0; j < GROWS; ++j) {
-                        // the second output's rows are gdel floats away (gdel < 0
-                        // for q > N/4): the offset is formed in 32 bits, where it
-                        // wraps to the true (nonnegative) offset, before the add
-                        const uint32_t go = goff[j] + (uint32_t)(o * gdel) * 4u;
-                        gn[b][o][j] = *(const float *)(gp + go);
-                    }
+                    for (int j = 0; j < GROWS; ++j)
+                        gn[b][o][j] = (j < GROWS - 1 || GFULL)
+                                          ? *(const float *)(gp + j * gr4 + (uint32_t)(goff0 + od))
+                                          : *(const float *)(gp + (uint32_t)(goffl + od));
+                }
             }
         };
         // octant rows of slice k go to LDS buffer k&1, whose previous
@@ -319,7 +328,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                         ob[j][e] = mk(x.x - ux, x.y - uy);
                     }
                 }
-                EF::first(xb[j], lds, c, ES, t);
+                EF::first_db(xb[j], lds, c, ES, t);
                 cx<float> v[E];
                 if constexpr (EF::NP == 1) {
 #pragma unroll
@@ -329,16 +338,16 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 // buffer j is free (both halves once the second output has
                 // entered its transform): refill it with slice k + PF
                 if constexpr (!PAR) fill(j, k + PF);
-                if constexpr (EF::NP > 1) EF::rest(xb[j], v, lds, c, ES, t, tws);
+                if constexpr (EF::NP > 1) EF::rest_db(xb[j], v, lds, lds2, c, ES, t, tws);
                 mac(0, glk, v);
                 if constexpr (PAR) {
-                    EF::first(ob[j], lds, c, ES, t);   // (its barrier: readers of the first output are done)
+                    EF::first_db(ob[j], lds, c, ES, t);
                     if constexpr (EF::NP == 1) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) v[e] = ob[j][e];
                     }
                     fill(j, k + PF);
-                    if constexpr (EF::NP > 1) EF::rest(ob[j], v, lds, c, ES, t, tws);
+                    if constexpr (EF::NP > 1) EF::rest_db(ob[j], v, lds, lds2, c, ES, t, tws);
                     mac(1, glk, v);
                 }
                 // stored at the end of the slice, after the refill loads were
@@ -361,7 +370,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                     if (o == 0 && has_dc && EF::out_pos(t, e) == 0) y[e] = mk(0.f, 0.f);
                 }
                 // the last forward pass's placement is the first inverse pass's
-                EI::run(y, lds, c, ES, t, tws);
+                EI::run_db(y, lds, lds2, c, ES, t, tws);
                 if (primary) {
                     cx<float> *dst = a.acc + (int64_t)b * a.acc_stride + o * obase;
                     if (col_ok)
