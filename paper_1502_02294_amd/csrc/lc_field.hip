@@ -455,12 +455,23 @@ __global__ __launch_bounds__(256) void fused_rest_merge_kernel(RestMerge m, ColS
     const int64_t H = m.L / 2;
     const int64_t obase = is_main ? H * H : H;
     const int64_t U = m.rest * m.kmax, lo = i * m.kmax, hi = lo + m.kmax;
+    // workgroups whose range starts inside the tile: w U / P in (lo, hi),
+    // i.e. w in [ceil((lo + 1) P / U), ceil(hi P / U)); eight loads in
+    // flight at a time, summed in a fixed order
+    const int64_t w0 = ((lo + 1) * m.P + U - 1) / U;
+    const int64_t w1 = std::min<int64_t>(m.P, (hi * m.P + U - 1) / U);
+    const cx<float> *src = m.part + (int64_t)b * m.part_stride + o * per + e;
     cx<float> v = mk(0.f, 0.f);
-    // first workgroup whose range starts after unit lo: w U / P >= lo + 1
-    for (int64_t w = ((lo + 1) * m.P + U - 1) / U; w < m.P; ++w) {
-        const int64_t a0 = w * U / m.P, a1 = (w + 1) * U / m.P;
-        if (a0 >= hi) break;
-        if (a1 > a0) v = v + m.part[(int64_t)b * m.part_stride + (m.no * w + o) * per + e];
+    for (int64_t w = w0; w < w1; w += 8) {
+        cx<float> t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t ww = w + j;
+            const bool on = ww < w1 && (ww + 1) * U / m.P > ww * U / m.P;   // non-empty range
+            t[j] = on ? src[m.no * ww * per] : mk(0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v = v + t[j];
     }
     cx<float> *dst = m.acc + (int64_t)b * m.acc_stride + o * obase + col_base(s, col) + (int64_t)z * s.row_stride;
     *dst = *dst + v;

@@ -483,6 +483,11 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
 // at some cost), so the fastest forward shape and fused schedule are found
 // per layout and the layout with the least K * (forward time per slice) +
 // (fused pass time) is kept. Spectra and DC partials are cleared afterwards.
+// Candidates are visited from the preferred end (larger slice groups, lower
+// shape numbers) and replace the current choice only when at least 2%
+// faster, so that shapes within timing noise of each other do not change the
+// choice from one plan to the next.
+constexpr double kTuneMargin = 0.98;
 int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     const int n = bp.n;
     const int reps = 3;
@@ -495,8 +500,8 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     {
         std::vector<int> cands;
         const int gmax = std::min(bp.K, SrcTab::kMax);
-        for (int g = 1; g < gmax; g *= 2) cands.push_back(g);
         cands.push_back(gmax);   // all slices (up to the table size) in one launch
+        for (int g = 1; g < gmax; g *= 2) cands.insert(cands.begin() + 1, g);   // then halvings, largest first
         for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v) {
             const int lay = v >= 0 && xy_parity(n, v) ? 1 : 0;
             if (lay == 1 && !fused_parity_supported(n)) continue;
@@ -507,7 +512,7 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
                 }, &ms);
                 if (rc) return rc;
                 fwd_seen[lay] = true;
-                if (ms / g < fwd_best[lay]) { fwd_best[lay] = ms / g; fwd_v[lay] = v; fwd_g[lay] = g; }
+                if (ms / g < kTuneMargin * fwd_best[lay]) { fwd_best[lay] = ms / g; fwd_v[lay] = v; fwd_g[lay] = g; }
             }
         }
     }
@@ -529,7 +534,7 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
                     return launch_col_y_inv_combine(n, bp.acc, bp.tw_full, bp.split_tab, bp.part, p->stream);
                 }, &ms);
                 if (rc) return rc;
-                if (ms < fz_best[lay]) { fz_best[lay] = ms; fz_v[lay] = v; fz_r[lay] = r; }
+                if (ms < kTuneMargin * fz_best[lay]) { fz_best[lay] = ms; fz_v[lay] = v; fz_r[lay] = r; }
             }
     }
     const int lay = fwd_seen[1] && (!fwd_seen[0] || bp.K * fwd_best[1] + fz_best[1] < bp.K * fwd_best[0] + fz_best[0])
