@@ -424,8 +424,10 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 // tiles (u = i kmax + k for remaining tile i) belongs to workgroup w with
 // w U / P <= u < (w + 1) U / P, U = rest kmax. The workgroup whose range holds
 // unit i kmax wrote tile i to the accumulator; every other workgroup whose
-// range starts inside tile i left its part in slot NO w + o (output o). One
-// thread per (tile, output, band, element) adds them in workgroup order.
+// range starts inside tile i left its part in slot NO w + o (output o).
+// The parts are added in a fixed order (within each quarter of the range in
+// workgroup order, then the quarters in order), so the result does not
+// depend on timing.
 struct RestMerge {
     cx<float> *acc;
     int64_t acc_stride;
@@ -436,16 +438,49 @@ struct RestMerge {
     int32_t npb, gp, nrow;
 };
 
+// Workgroup: 64 consecutive elements of one (tile, output, band); its four
+// waves sum a quarter of the parts each (eight loads in flight at a time)
+// and wave 0 adds the four partial sums in wave order.
 __global__ __launch_bounds__(256) void fused_rest_merge_kernel(RestMerge m, ColSet s0, ColSet s1) {
+    __shared__ cx<float> red[3][64];
     const int64_t per = (int64_t)m.L * m.cpw;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m.rest * m.no * m.nband * per) return;
-    const int64_t e = idx % per;
-    int64_t r = idx / per;
+    const int64_t chunks = (per + 63) / 64;
+    const int64_t g = blockIdx.x;
+    const int64_t ch = g % chunks;
+    int64_t r = g / chunks;
     const int b = (int)(r % m.nband);
     r /= m.nband;
     const int o = (int)(r % m.no);
     const int64_t i = r / m.no;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t e = ch * 64 + lane;
+    const bool ok_e = e < per;
+    const int64_t U = m.rest * m.kmax, lo = i * m.kmax, hi = lo + m.kmax;
+    // workgroups whose range starts inside the tile: w U / P in (lo, hi),
+    // i.e. w in [ceil((lo + 1) P / U), ceil(hi P / U))
+    const int64_t w0 = ((lo + 1) * m.P + U - 1) / U;
+    const int64_t w1 = std::min<int64_t>(m.P, (hi * m.P + U - 1) / U);
+    const int64_t nq = (w1 - w0 + 3) / 4;
+    const int64_t qa = w0 + wv * nq, qb = std::min<int64_t>(w1, qa + nq);
+    const cx<float> *src = m.part + (int64_t)b * m.part_stride + o * per + (ok_e ? e : 0);
+    cx<float> v = mk(0.f, 0.f);
+    for (int64_t w = qa; w < qb; w += 8) {
+        cx<float> t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t ww = w + j;
+            const bool on = ok_e && ww < qb && (ww + 1) * U / m.P > ww * U / m.P;   // non-empty range
+            t[j] = on ? src[m.no * ww * per] : mk(0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v = v + t[j];
+    }
+    if (wv > 0) red[wv - 1][lane] = v;
+    __syncthreads();
+    if (wv > 0 || !ok_e) return;
+    v = v + red[0][lane];
+    v = v + red[1][lane];
+    v = v + red[2][lane];
     const int z = (int)(e / m.cpw), c = (int)(e % m.cpw);
     const int64_t tile = fused_slot_tile(m.full + i, s0.n_wgs, m.nrow, m.npb, m.gp);
     const bool is_main = tile < s0.n_wgs;
@@ -454,25 +489,6 @@ __global__ __launch_bounds__(256) void fused_rest_merge_kernel(RestMerge m, ColS
     if (col >= s.n_cols) return;
     const int64_t H = m.L / 2;
     const int64_t obase = is_main ? H * H : H;
-    const int64_t U = m.rest * m.kmax, lo = i * m.kmax, hi = lo + m.kmax;
-    // workgroups whose range starts inside the tile: w U / P in (lo, hi),
-    // i.e. w in [ceil((lo + 1) P / U), ceil(hi P / U)); eight loads in
-    // flight at a time, summed in a fixed order
-    const int64_t w0 = ((lo + 1) * m.P + U - 1) / U;
-    const int64_t w1 = std::min<int64_t>(m.P, (hi * m.P + U - 1) / U);
-    const cx<float> *src = m.part + (int64_t)b * m.part_stride + o * per + e;
-    cx<float> v = mk(0.f, 0.f);
-    for (int64_t w = w0; w < w1; w += 8) {
-        cx<float> t[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t ww = w + j;
-            const bool on = ww < w1 && (ww + 1) * U / m.P > ww * U / m.P;   // non-empty range
-            t[j] = on ? src[m.no * ww * per] : mk(0.f, 0.f);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v = v + t[j];
-    }
     cx<float> *dst = m.acc + (int64_t)b * m.acc_stride + o * obase + col_base(s, col) + (int64_t)z * s.row_stride;
     *dst = *dst + v;
 }
@@ -589,9 +605,8 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
         m.npb = (N / 2) % CPW == 0 ? (N / 2) / CPW : 0;
         m.gp = CPW >= 32 ? 1 : 32 / CPW;
         m.nrow = PAR ? N / 2 : N;
-        const int64_t threads = m.rest * m.no * m.nband * (int64_t)N * CPW;
-        hipLaunchKernelGGL(fused_rest_merge_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m,
-                           s0, s1);
+        const int64_t wgs = m.rest * m.no * m.nband * (((int64_t)N * CPW + 63) / 64);
+        hipLaunchKernelGGL(fused_rest_merge_kernel, dim3((unsigned)wgs), dim3(256), 0, st, m, s0, s1);
     }
     return hipGetLastError();
 }
