@@ -70,6 +70,7 @@ def bytes_model(n, K, B, fused, csz, rsz):
         "col_y_fwd": 2 * spec,                # read + write one spectrum
         "col_y_inv": 2 * spec,
         "x_inv": spec + n3 * rsz,             # read spectrum, write the field
+        "yx_inv": spec + n3 * rsz,            # fused inverse y + x (parity layout): read A, write the field
     }
     if fused:
         m["fused_z"] = K * (spec + octb) + B * spec   # every slice + its kernel octant, write A once
@@ -120,8 +121,14 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
         else:
             ids = {"x_fwd": lc.LC_KERNEL_X_FWD, "col_y_fwd": lc.LC_KERNEL_COL_Y_FWD}
             per_step = {"x_fwd": K, "col_y_fwd": K}
-        ids.update({"col_y_inv": lc.LC_KERNEL_COL_Y_INV, "x_inv": lc.LC_KERNEL_X_INV})
-        per_step.update({"col_y_inv": B, "x_inv": B})
+        # the parity-layout schedule fuses the inverse y and x passes
+        try:
+            plan.time_kernel(lc.LC_KERNEL_YX_INV, 0, 1)
+            ids["yx_inv"] = lc.LC_KERNEL_YX_INV
+            per_step["yx_inv"] = B
+        except lc.LCError:
+            ids.update({"col_y_inv": lc.LC_KERNEL_COL_Y_INV, "x_inv": lc.LC_KERNEL_X_INV})
+            per_step.update({"col_y_inv": B, "x_inv": B})
         if fused:
             ids["fused_z"] = lc.LC_KERNEL_FUSED_Z
             per_step["fused_z"] = (B + 1) // 2

@@ -211,9 +211,13 @@ typedef enum {
     LC_KERNEL_COL_Z_INV = 5,  /* inverse z pass of one band (unfused forms)           */
     LC_KERNEL_COL_Y_INV = 6,  /* inverse y pass of one band                           */
     LC_KERNEL_X_INV = 7,      /* inverse x pass + epilogue of one band                */
-    LC_KERNEL_XY_FWD = 8      /* fused forward x + y pass of one slice (FP32 form,
+    LC_KERNEL_XY_FWD = 8,     /* fused forward x + y pass of one slice (FP32 form,
                                  N in {64, 96, 128, 192, 256}, where the step uses it
                                  in place of LC_KERNEL_X_FWD + LC_KERNEL_COL_Y_FWD)   */
+    LC_KERNEL_YX_INV = 9      /* fused inverse y + x pass + epilogue of one band (FP32
+                                 form with a parity-layout xy shape, where the step
+                                 uses it in place of LC_KERNEL_COL_Y_INV +
+                                 LC_KERNEL_X_INV)                                      */
 } lc_kernel_id;
 
 /* Launch shapes of one box's tunable passes (a6: radix schedule, columns

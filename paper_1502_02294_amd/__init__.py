@@ -31,7 +31,7 @@ EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources
             "lc_time_kernel", "lc_get_schedule", "lc_set_schedule"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
- LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD) = range(9)
+ LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD, LC_KERNEL_YX_INV) = range(10)
 
 
 class lc_box_desc(C.Structure):

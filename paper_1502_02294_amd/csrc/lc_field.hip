@@ -359,30 +359,50 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // the (0,0,0) bin: row 0 of main column 0
         const bool has_dc = a.zero_dc && is_main && col == 0;
         const bool primary = k0 == 0;
+        auto put = [&](int b, int o, const cx<float>(&y)[E]) {
+            if (primary) {
+                cx<float> *dst = a.acc + (int64_t)b * a.acc_stride + o * obase;
+                if (col_ok)
 #pragma unroll
-        for (int o = 0; o < NO; ++o)
+                    for (int e = 0; e < E; ++e)
+                        dst[(uint32_t)(cbase + (int64_t)EI::out_pos(t, e) * s.row_stride)] = y[e];
+            } else {
+                cx<float> *dst = a.part + (int64_t)b * a.part_stride + (int64_t)(NO * w + o) * (L * CPW) + c;
 #pragma unroll
-            for (int b = 0; b < NB_; ++b) {
-                cx<float> y[E];
+                for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
+            }
+        };
+#pragma unroll
+        for (int b = 0; b < NB_; ++b) {
+            cx<float> y[NO][E];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    y[e] = sum[o][b][e] - cmp[o][b][e];
-                    if (o == 0 && has_dc && EF::out_pos(t, e) == 0) y[e] = mk(0.f, 0.f);
+                    y[o][e] = sum[o][b][e] - cmp[o][b][e];
+                    if (o == 0 && has_dc && EF::out_pos(t, e) == 0) y[o][e] = mk(0.f, 0.f);
                 }
                 // the last forward pass's placement is the first inverse pass's
-                EI::run_db(y, lds, lds2, c, ES, t, tws);
-                if (primary) {
-                    cx<float> *dst = a.acc + (int64_t)b * a.acc_stride + o * obase;
-                    if (col_ok)
+                EI::run_db(y[o], lds, lds2, c, ES, t, tws);
+            }
+            if constexpr (PAR) {
+                // first radix-2 step of the inverse y transform, split by the
+                // parity s of the output rows y = 2m + s:
+                //   U_0 = T[q] + T[q + N/2],  U_1 = W_N^-q (T[q] - T[q + N/2])
+                // (the inverse y pass of rows of parity s is the N/2-point
+                // inverse transform of U_s), stored in the places of T[q] and
+                // T[q + N/2]
 #pragma unroll
-                        for (int e = 0; e < E; ++e)
-                            dst[(uint32_t)(cbase + (int64_t)EI::out_pos(t, e) * s.row_stride)] = y[e];
-                } else {
-                    cx<float> *dst = a.part + (int64_t)b * a.part_stride + (int64_t)(NO * w + o) * (L * CPW) + c;
-#pragma unroll
-                    for (int e = 0; e < E; ++e) dst[EI::out_pos(t, e) * CPW] = y[e];
+                for (int e = 0; e < E; ++e) {
+                    const cx<float> u = y[0][e], v = y[1][e];
+                    const cx<float> d = mk(u.x - v.x, u.y - v.y);
+                    y[0][e] = mk(u.x + v.x, u.y + v.y);
+                    y[1][e] = mk(fmaf(wq.x, d.x, wq.y * d.y), fmaf(wq.x, d.y, -wq.y * d.x));   // conj(W^q) d
                 }
             }
+#pragma unroll
+            for (int o = 0; o < NO; ++o) put(b, o, y[o]);
+        }
         };
     if (a.rounds) {
         // whole tiles in rounds: all workgroups sweep the slices together

@@ -835,8 +835,14 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
                 char *acc = bp.acc + (size_t)(b + j) * se * cs;
-                HIPCHK(launch_col_y_inv_combine(n, acc, bp.tw_full, tab,
-                                                bp.part + (size_t)j * bp.part_stride * 8, st));
+                char *part = bp.part + (size_t)j * bp.part_stride * 8;
+                if (fa.parity) {
+                    // parity-layout accumulator: inverse y + x fused per half plane
+                    HIPCHK(launch_yx_inv(n, acc, outp[b + j - b0], out_f64, bp.tw_half, bp.twist, bp.tw_full,
+                                         inv_n3, bp.mu + b + j, tab, fa.rounds ? nullptr : part, st));
+                    continue;
+                }
+                HIPCHK(launch_col_y_inv_combine(n, acc, bp.tw_full, tab, part, st));
                 HIPCHK(launch_x_inv(n, false, acc, outp[b + j - b0], out_f64, bp.tw_half, bp.twist, inv_n3,
                                     bp.mu + b + j, st));
             }
@@ -1038,9 +1044,13 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
         if (!bp.built[b]) return fail(LC_ESTATE, "kernels not built");
     const bool fused = p->prec == LC_PREC_FP32;
     const bool plain_only = kernel == LC_KERNEL_COL_Z_FWD || kernel == LC_KERNEL_MAC || kernel == LC_KERNEL_COL_Z_INV;
-    if (kernel < 0 || kernel > LC_KERNEL_XY_FWD) return fail(LC_EINVAL, "unknown kernel id %d", kernel);
+    if (kernel < 0 || kernel > LC_KERNEL_YX_INV) return fail(LC_EINVAL, "unknown kernel id %d", kernel);
     if (kernel == LC_KERNEL_XY_FWD && !bp.use_xy)
         return fail(LC_EINVAL, "this plan does not use the fused xy pass (FP32 form, N in 64..256)");
+    if (kernel == LC_KERNEL_YX_INV && !bp.parity())
+        return fail(LC_EINVAL, "the fused inverse y + x pass belongs to the parity-layout schedule");
+    if ((kernel == LC_KERNEL_COL_Y_INV || kernel == LC_KERNEL_X_INV) && bp.parity())
+        return fail(LC_EINVAL, "the parity-layout schedule runs the fused inverse y + x pass instead");
     if (fused && plain_only) return fail(LC_EINVAL, "kernel %d is not part of the fused form", kernel);
     if (!fused && kernel == LC_KERNEL_FUSED_Z) return fail(LC_EINVAL, "the fused z pass belongs to LC_PREC_FP32");
     const int n = bp.n;
@@ -1098,6 +1108,9 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
             case LC_KERNEL_COL_Y_INV:
                 return fused ? launch_col_y_inv_combine(n, acc0, bp.tw_full, bp.split_tab, bp.part, st)
                              : launch_col(n, p->t_f64, 1, false, acc0, bp.tw_full, st);
+            case LC_KERNEL_YX_INV:
+                return launch_yx_inv(n, acc0, p->scratch_real, false, bp.tw_half, bp.twist, bp.tw_full,
+                                     1.0 / (double)n3, bp.mu, bp.split_tab, bp.fused_rounds ? nullptr : bp.part, st);
             default:
                 return launch_x_inv(n, p->t_f64, acc0, p->scratch_real, p->t_f64, bp.tw_half, bp.twist,
                                     1.0 / (double)n3, fused ? bp.mu : nullptr, st);

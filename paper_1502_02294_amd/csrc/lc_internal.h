@@ -54,6 +54,15 @@ hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bo
 bool xy_supported(int n);
 int xy_variants(int n);
 bool xy_parity(int n, int variant);
+// Inverse y + x passes and epilogue of one band's FP32 accumulator in the
+// parity layout left by the fused z pass with parity input (rows q and
+// N/2 + q hold U_0 = T[q] + T[q+N/2] and U_1 = W_N^-q (T[q] - T[q+N/2])):
+// out = IDFT(acc) * scale + *mu, N^3 reals (FP32 or FP64). With part
+// non-null the second parts of split fused tiles (split_tab) are added.
+bool yx_inv_supported(int n);
+hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const void *tw_half, const void *twist,
+                         const void *tw_full, double scale, const double *mu, const int *split_tab,
+                         const void *part, hipStream_t st);
 hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
                                const void *tw_half, const void *twist, const void *tw_full, double *dcpart,
                                int64_t dc_stride, int variant, hipStream_t st);

@@ -337,6 +337,168 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_, NR_>::NT)) void xy_fwd_ke
     }
 }
 
+// Inverse y and x passes and the epilogue of Eq. 12's inverse transform,
+// fused per half z-plane, for an FP32 accumulator in the parity layout (the
+// fused z pass with parity input leaves, in rows q and N/2 + q of every
+// z-plane, U_0 = T[q] + T[q + N/2] and U_1 = W_N^-q (T[q] - T[q + N/2])).
+// Output rows y = 2m + s of one z-plane are the N/2-point inverse y
+// transform of U_s, so a workgroup takes (z, s), reads its half plane once
+// and writes N/2 output rows once:
+//   1. column batch by column batch (lanes walk the columns), the N/2-point
+//      inverse y transform in registers; the p = 0 and p = N/2 columns, whose
+//      inverse transforms are real, travel packed as U_s[.][0] + i U_s[.][N/2];
+//   2. row batch by row batch, the rows are transposed through LDS and each
+//      goes through the complex-to-real x transform (the retangle
+//      Z[p] = E'_p + i O'_p of the half-length trick, then the N/2-point
+//      inverse transform), scaled by 1/N^3, plus the FP64 mean, and stored.
+// With COMBINE the second parts of tiles that the fused pass split between
+// two workgroups (tab, part) are added while loading.
+template <int N, typename TOUT, bool S8, int NB_, bool COMBINE>
+__global__ __launch_bounds__((XYShape<N, S8, NB_, 0, N / 2>::NT)) void yx_inv_kernel(
+    const cx<float> *__restrict__ acc, TOUT *__restrict__ out, const cx<float> *__restrict__ tw_half,
+    const cx<float> *__restrict__ twist, const cx<float> *__restrict__ tw_full, double scale,
+    const double *__restrict__ mu, const int *__restrict__ tab, const cx<float> *__restrict__ part, int cpw_z,
+    int64_t tiles_main) {
+    using SH = XYShape<N, S8, NB_, 0, N / 2>;
+    constexpr int L = SH::L, NR = SH::NR, TX = SH::TX, TY = SH::TY, NB = SH::NB, RPB = SH::RPB, CPB = SH::CPB;
+    constexpr int NT = SH::NT, SK = SH::SK, LSX = SH::LSX;
+    using EY = Engine<float, NR, false, typename SH::SY>;
+    using EX = Engine<float, L, false, typename SH::SX, SK>;
+    constexpr int EYN = EY::E, EXN = EX::E;
+    constexpr int RLY = EY::RL, BPTY = EY::PLs::BPT;
+    static_assert(RPB % TY == 0, "a y output row's batch is fixed by its element index");
+    constexpr int ESY = CPB + 1;                 // y exchange: [row][column of the batch]
+    constexpr int LSR = L + 1;                   // transposed row batch: [row][p], p = 0 packed
+    constexpr int YREG = NR * ESY, RREG = RPB * LSR, XREG = RPB * LSX;
+    constexpr int LDSN = YREG > RREG + XREG ? YREG : RREG + XREG;
+    static_assert((LDSN + 2 * L + NR) * 8 <= 80 * 1024, "two workgroups per CU");
+    __shared__ cx<float> lds[LDSN];
+    __shared__ cx<float> twx[L], twt[L], twy[NR];
+
+    const int tid = threadIdx.x;
+    const int yc = tid % CPB, yt = tid / CPB;
+    const int xl = tid / TX, xt = tid % TX;
+    const int z = blockIdx.x / 2, sp = blockIdx.x % 2;
+    const cx<float> *__restrict__ mainp = acc + ((int64_t)z * N + sp * NR) * L;
+    const cx<float> *__restrict__ nyq = acc + spec_main(N) + (int64_t)z * N + sp * NR;
+
+    // every column batch of the half plane, loaded up front
+    cx<float> yr[NB][EYN];
+    auto part_at = [&](int64_t zt, int zc) -> cx<float> {
+        const int w = tab[zt];
+        return w >= 0 ? part[((int64_t)w * N + z) * cpw_z + zc] : mk(0.f, 0.f);
+    };
+    static_for<NB>([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
+        const int p = cb * CPB + yc;
+#pragma unroll
+        for (int e = 0; e < EYN; ++e) {
+            const int r = EY::in_pos(yt, e);
+            if (p != 0) {
+                cx<float> v = mainp[(int64_t)r * L + p];
+                if constexpr (COMBINE) {
+                    const int64_t cc = (int64_t)(sp * NR + r) * L + p;
+                    v = v + part_at(cc / cpw_z, (int)(cc % cpw_z));
+                }
+                yr[cb][e] = v;
+            } else {
+                cx<float> a = mainp[(int64_t)r * L], b = nyq[r];
+                if constexpr (COMBINE) {
+                    const int64_t cc = (int64_t)(sp * NR + r) * L;
+                    a = a + part_at(cc / cpw_z, (int)(cc % cpw_z));
+                    const int q = sp * NR + r;
+                    b = b + part_at(tiles_main + q / cpw_z, q % cpw_z);
+                }
+                yr[cb][e] = mk(a.x - b.y, a.y + b.x);   // a + i b
+            }
+        }
+    });
+    for (int i = tid; i < L; i += NT) {
+        twx[i] = tw_half[i];
+        twt[i] = twist[i];
+    }
+    for (int i = tid; i < NR; i += NT) twy[i] = tw_full[2 * i];   // W_NR^i = W_N^(2i)
+    lds_barrier();
+
+    // ---- 1. inverse y transforms, one column batch at a time (in place)
+    static_for<NB>([&](auto cbc) {
+        constexpr int cb = decltype(cbc)::value;
+        EY::run(yr[cb], lds, yc, ESY, yt, twy);
+    });
+
+    // ---- 2. per row batch: transpose, C2R x transform, epilogue
+    const double m = *mu;
+    cx<float> *rreg = lds, *xreg = lds + RREG;
+    static_for<NB>([&](auto rbc) {
+        constexpr int rb = decltype(rbc)::value;
+        lds_barrier();   // earlier readers of the row and exchange regions are done
+        static_for<NB>([&](auto cbc) {
+            constexpr int cb = decltype(cbc)::value;
+#pragma unroll
+            for (int e = 0; e < EYN; ++e) {
+                // output row of element e: yt + TY (i + r BPT), i = e / RL, r = e % RL
+                const int j = e / RLY + (e % RLY) * BPTY;
+                if ((TY * j) / RPB == rb) rreg[(EY::out_pos(yt, e) - rb * RPB) * LSR + cb * CPB + yc] = yr[cb][e];
+            }
+        });
+        lds_barrier();
+        const cx<float> *row = rreg + xl * LSR;
+        cx<float> zx[EXN];
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            const int q = EX::in_pos(xt, e);
+            if (q == 0) {
+                const cx<float> pk = row[0];   // (Y[y][0], Y[y][N/2]), both real
+                zx[e] = mk(pk.x + pk.y, pk.x - pk.y);
+            } else {
+                // Z[q] = E'_q + i O'_q,  E'_q = X[q] + conj X[L-q],  O'_q = (X[q] - conj X[L-q]) conj(W^q)
+                const cx<float> Xp = row[q], Xm = row[L - q];
+                const cx<float> Ep = mk(Xp.x + Xm.x, Xp.y - Xm.y);
+                const cx<float> Dp = mk(Xp.x - Xm.x, Xp.y + Xm.y);
+                const cx<float> w = twt[q];
+                const cx<float> Op = mk(Dp.x * w.x + Dp.y * w.y, Dp.y * w.x - Dp.x * w.y);
+                zx[e] = mk(Ep.x - Op.y, Ep.y + Op.x);
+            }
+        }
+        EX::run(zx, xreg, xl * LSX, 1, xt, twx);
+        const int y = 2 * (rb * RPB + xl) + sp;
+        TOUT *orow = out + ((int64_t)z * N + y) * N;
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            cx<TOUT> o;
+            o.x = (TOUT)((double)zx[e].x * scale + m);
+            o.y = (TOUT)((double)zx[e].y * scale + m);
+            *(cx<TOUT> *)(orow + 2 * EX::out_pos(xt, e)) = o;
+        }
+    });
+}
+
+bool yx_inv_supported(int n) { return n == 256; }
+
+hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const void *tw_half, const void *twist,
+                         const void *tw_full, double scale, const double *mu, const int *split_tab,
+                         const void *part, hipStream_t st) {
+    if (n != 256 || !mu) return hipErrorInvalidValue;
+    constexpr int N = 256;
+    constexpr bool S8 = false;
+    constexpr int NB = 4;
+    using SH = XYShape<N, S8, NB, 0, N / 2>;
+    const int cpw = fused_cpw(N);
+    const int64_t tiles_main = (int64_t)N * (N / 2) / cpw;
+    const dim3 grid(2 * N);
+#define YI_(TOUT, COMB)                                                                                       \
+    hipLaunchKernelGGL((yx_inv_kernel<N, TOUT, S8, NB, COMB>), grid, dim3(SH::NT), 0, st, (const cx<float> *)acc, \
+                       (TOUT *)out, (const cx<float> *)tw_half, (const cx<float> *)twist,                       \
+                       (const cx<float> *)tw_full, scale, mu, split_tab, (const cx<float> *)part, cpw, tiles_main)
+    if (part) {
+        if (out_f64) YI_(double, true); else YI_(float, true);
+    } else {
+        if (out_f64) YI_(double, false); else YI_(float, false);
+    }
+#undef YI_
+    return hipGetLastError();
+}
+
 bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
 
 // Launch shapes compiled per N (schedule, batches); the plan picks one.

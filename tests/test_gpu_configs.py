@@ -283,6 +283,8 @@ def test_time_kernel_reports_positive_durations():
         assert plan.time_kernel(kid, 0, 2) > 0.0
     with pytest.raises(lc.LCError):
         plan.time_kernel(lc.LC_KERNEL_MAC, 0, 2)     # not part of the fused form
+    with pytest.raises(lc.LCError):
+        plan.time_kernel(lc.LC_KERNEL_YX_INV, 0, 2)  # parity-layout schedules only
     plan.close()
 
 

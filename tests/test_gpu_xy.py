@@ -92,8 +92,11 @@ def test_parity_layout_every_fused_schedule(nbands):
     """The half-plane xy shapes leave the y transforms of the even and the odd
     rows apart (T[q] = E[q mod N/2] + W_N^q O[q mod N/2], Sec. 2.2's FFT
     route with the last radix-2 step of the y transform deferred); the fused
-    z pass completes them. Every register schedule, both scheduling modes,
-    one and two bands per launch, against the oracle on sampled cells."""
+    z pass completes them and leaves the first radix-2 step of the inverse y
+    transform split by output-row parity, which the fused inverse y + x pass
+    takes per half plane. Every register schedule, both scheduling modes
+    (split-tile parts added by the inverse pass), one and two bands per
+    launch, FP32 and FP64 output, against the oracle on sampled cells."""
     lc = _lc()
     n, K = 256, 3
     box = _box(n, K=K, seed=31 + nbands)
@@ -119,10 +122,17 @@ def test_parity_layout_every_fused_schedule(nbands):
                 print(f"case parity nbands={nbands} xy={xv} fused={fv} rounds={r}", flush=True)
                 plan.set_schedule(0, xy_variant=xv, fused_variant=fv, fused_rounds=r)
                 for b in range(nbands):
-                    J = plan.field(0, b).double().cpu().numpy().ravel()
+                    # (FP64 output once: the fused inverse pass's FP64 epilogue)
+                    dt = torch.float64 if (fv, r, b) == (1, 1, 0) else None
+                    J = plan.field(0, b, dtype=dt).double().cpu().numpy().ravel()
                     e_max, e_rms = oracle.rel_errors(J[tg], Jr[b])
                     print(f"  band={b} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
                     assert e_rms <= 1e-5 and e_max <= 1e-4
+    # the parity-layout step runs the fused inverse y + x pass
+    assert plan.time_kernel(lc.LC_KERNEL_YX_INV, 0, 2) > 0.0
+    for kid in (lc.LC_KERNEL_COL_Y_INV, lc.LC_KERNEL_X_INV):
+        with pytest.raises(lc.LCError):
+            plan.time_kernel(kid, 0, 2)
     plan.close()
 
 
