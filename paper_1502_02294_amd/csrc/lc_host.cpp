@@ -483,10 +483,10 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
 // at some cost), so the fastest forward shape and fused schedule are found
 // per layout and the layout with the least K * (forward time per slice) +
 // (fused pass time) is kept. Spectra and DC partials are cleared afterwards.
-// Candidates are visited from the preferred end (larger slice groups, lower
-// shape numbers) and replace the current choice only when at least 2%
-// faster, so that shapes within timing noise of each other do not change the
-// choice from one plan to the next.
+// Candidates are visited from the preferred end (lower shape numbers) and
+// replace the current choice only when at least 2% faster, so that shapes
+// within timing noise of each other do not change the choice from one plan
+// to the next.
 constexpr double kTuneMargin = 0.98;
 int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     const int n = bp.n;
@@ -498,10 +498,10 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     int fwd_v[2] = {-1, -1}, fwd_g[2] = {bp.push_group, bp.push_group};
     bool fwd_seen[2] = {false, false};
     {
-        std::vector<int> cands;
-        const int gmax = std::min(bp.K, SrcTab::kMax);
-        cands.push_back(gmax);   // all slices (up to the table size) in one launch
-        for (int g = 1; g < gmax; g *= 2) cands.insert(cands.begin() + 1, g);   // then halvings, largest first
+        // all slices (up to the table size) in one launch: smaller groups
+        // changed the per-slice time by about 1%, less than the trial-to-trial
+        // spread, so tuning the grouping only made the choice unstable
+        std::vector<int> cands{std::min(bp.K, SrcTab::kMax)};
         for (int v = bp.use_xy ? 0 : -1; v < (bp.use_xy ? xy_variants(n) : 0); ++v) {
             const int lay = v >= 0 && xy_parity(n, v) ? 1 : 0;
             if (lay == 1 && !fused_parity_supported(n)) continue;
