@@ -92,6 +92,10 @@ struct FusedDev {
     int64_t W;
     int32_t rounds;            // 1: whole tiles w, w+P, ... (no split tiles)
     int64_t tiles;
+    const double *sk, *g0;     // band means (mu non-null): see FusedArgs
+    double inv_n3;
+    double *mu;
+    int32_t K;
 };
 
 // Processing order of the main tiles in the rounds schedule. Main tile
@@ -154,6 +158,17 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     // double buffered by slice: rows r and L-r of a column share one entry
     __shared__ float gl[2][NB_ * NO][HP * CPW];
     for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
+    // the FP64 band means (DC mode), once per launch, by the first wave of
+    // workgroup 0: mu_b = inv_n3 sum_k G^_{k,b}(0) S^_k(0)
+    if (a.mu && blockIdx.x == 0 && threadIdx.x < 64) {
+#pragma unroll
+        for (int b = 0; b < NB_; ++b) {
+            double v = 0.0;
+            for (int k = threadIdx.x; k < a.K; k += 64) v += a.g0[(int64_t)k * a.B + a.band0 + b] * a.sk[k];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (threadIdx.x == 0) a.mu[a.band0 + b] = v * a.inv_n3;
+        }
+    }
 
     const int c = threadIdx.x % CPW, t = threadIdx.x / CPW;
     const int H = L / 2;
@@ -599,11 +614,10 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
     d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
     d.rounds = fa.rounds; d.tiles = tiles;
-    const int64_t std_tiles = PAR ? 2 * tiles : tiles;   // the table covers the tiles of every output row
-    if (fa.rounds)   // no tile is split: every entry -1
-        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((std_tiles + 255) / 256)), dim3(256), 0, st,
-                           (int *)fa.split_tab, std_tiles, (int64_t)1, (int64_t)1, std_tiles, 0, (int64_t)0);
-    else
+    d.sk = fa.sk; d.g0 = fa.g0; d.inv_n3 = fa.inv_n3; d.mu = fa.mu; d.K = fa.K;
+    // the split table serves the stream-K mode's merge in the inverse y pass;
+    // the rounds mode splits no tile and its inverse pass does not read it
+    if (!fa.rounds)
         hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
                            (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W, PAR ? 1 : 0, (int64_t)s0.n_wgs);
     constexpr int NT = FusedShape<N, S>::NT;
@@ -663,14 +677,20 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
     const int64_t std_tiles = fa.parity ? 2 * tiles : tiles;
     const int kmax = std::max(fa.kcount[0], fa.nband > 1 ? fa.kcount[1] : 0);
     if (kmax <= 0) {
-        // no slice contributes: the accumulators are zero
+        // no slice contributes: the accumulators are zero (and so are the
+        // kernels' DC values, hence the means)
+        if (fa.mu) {
+            hipError_t e = launch_fill_f64(fa.mu + fa.band0, fa.nband, 0.0, st);
+            if (e != hipSuccess) return e;
+        }
         for (int b = 0; b < fa.nband; ++b) {
             hipError_t e = launch_fill_bytes((char *)fa.acc + (size_t)b * fa.acc_stride * 8,
                                              fa.acc_stride * 8, st);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((std_tiles + 255) / 256)), dim3(256), 0, st,
-                           (int *)fa.split_tab, std_tiles, (int64_t)1, (int64_t)1, std_tiles, 0, (int64_t)0);
+        if (!fa.rounds)   // no tile split: every entry -1
+            hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((std_tiles + 255) / 256)), dim3(256), 0, st,
+                               (int *)fa.split_tab, std_tiles, (int64_t)1, (int64_t)1, std_tiles, 0, (int64_t)0);
         return hipGetLastError();
     }
     if constexpr (fused_par<N>()) {
@@ -757,7 +777,7 @@ __global__ __launch_bounds__(64) void dc_mu_kernel(const double *__restrict__ sk
 hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
                             double inv_n3, double *sk, double *mu, hipStream_t st) {
     hipLaunchKernelGGL(dc_slice_kernel, dim3(K), dim3(256), 0, st, dcpart, W, sk);
-    hipLaunchKernelGGL(dc_mu_kernel, dim3(1), dim3(64), 0, st, sk, K, g0, B, inv_n3, mu);
+    if (mu) hipLaunchKernelGGL(dc_mu_kernel, dim3(1), dim3(64), 0, st, sk, K, g0, B, inv_n3, mu);
     return hipGetLastError();
 }
 

@@ -433,6 +433,14 @@ template <typename F> int time_calls(hipStream_t st, int reps, F &&launch, doubl
     return LC_OK;
 }
 
+// Inverse y pass of an FP32 accumulator after the fused z pass: the stream-K
+// mode's split tiles are merged while loading; the rounds mode splits none.
+hipError_t inv_y_fused(int n, void *acc, const void *tw_full, const int *tab, const void *part, bool rounds,
+                       hipStream_t st) {
+    return rounds ? launch_col(n, false, 1, false, acc, tw_full, st)
+                  : launch_col_y_inv_combine(n, acc, tw_full, tab, part, st);
+}
+
 FusedArgs fused_args(const BoxPlan &bp) {
     FusedArgs fa;
     const int n = bp.n;
@@ -528,10 +536,19 @@ int autotune_box(lc_plan_t *p, BoxPlan &bp) {
                 bp.fused_rounds = r;
                 FusedArgs fa = fused_args(bp);
                 fa.parity = lay;
+                // with the layout's own inverse pass (fused inverse y + x for the
+                // parity layout; the inverse y pass otherwise, the x pass being
+                // the same in both)
                 int rc = time_calls(p->stream, 2, [&]() {
                     hipError_t e = launch_fused_z(n, fa, bp.tw_full, p->stream);
                     if (e != hipSuccess) return e;
-                    return launch_col_y_inv_combine(n, bp.acc, bp.tw_full, bp.split_tab, bp.part, p->stream);
+                    if (lay)
+                        return launch_yx_inv(n, bp.acc, p->scratch_real, false, bp.tw_half, bp.twist, bp.tw_full,
+                                             1.0, bp.mu, bp.split_tab, r ? nullptr : bp.part, p->stream);
+                    e = inv_y_fused(n, bp.acc, bp.tw_full, bp.split_tab, bp.part, r != 0, p->stream);
+                    if (e != hipSuccess) return e;
+                    return launch_x_inv(n, false, bp.acc, p->scratch_real, false, bp.tw_half, bp.twist, 1.0, nullptr,
+                                        p->stream);
                 }, &ms);
                 if (rc) return rc;
                 if (ms < kTuneMargin * fz_best[lay]) { fz_best[lay] = ms; fz_v[lay] = v; fz_r[lay] = r; }
@@ -817,7 +834,8 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
     const double inv_n3 = 1.0 / ((double)n * n * n);
     hipStream_t st = p->stream;
     if (p->prec == LC_PREC_FP32) {
-        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.ghat0, bp.B, inv_n3, bp.sk, bp.mu, st));
+        // per-slice input sums; the fused z pass reduces the band means
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.ghat0, bp.B, inv_n3, bp.sk, nullptr, st));
         for (int b = b0; b < b1;) {
             const int nb = std::min(2, b1 - b);
             int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;
@@ -832,6 +850,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.split_tab = tab;
             fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             fa.parity = bp.parity() ? 1 : 0;
+            fa.sk = bp.sk; fa.g0 = bp.ghat0; fa.inv_n3 = inv_n3; fa.mu = bp.mu;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
                 char *acc = bp.acc + (size_t)(b + j) * se * cs;
@@ -842,7 +861,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
                                          inv_n3, bp.mu + b + j, tab, fa.rounds ? nullptr : part, st));
                     continue;
                 }
-                HIPCHK(launch_col_y_inv_combine(n, acc, bp.tw_full, tab, part, st));
+                HIPCHK(inv_y_fused(n, acc, bp.tw_full, tab, part, fa.rounds != 0, st));
                 HIPCHK(launch_x_inv(n, false, acc, outp[b + j - b0], out_f64, bp.tw_half, bp.twist, inv_n3,
                                     bp.mu + b + j, st));
             }
@@ -1106,7 +1125,7 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                                         bp.ghat + (size_t)k * bp.B * oct_elems(n) * rs, false, st);
             case LC_KERNEL_COL_Z_INV: return launch_col(n, p->t_f64, 2, false, acc0, bp.tw_full, st);
             case LC_KERNEL_COL_Y_INV:
-                return fused ? launch_col_y_inv_combine(n, acc0, bp.tw_full, bp.split_tab, bp.part, st)
+                return fused ? inv_y_fused(n, acc0, bp.tw_full, bp.split_tab, bp.part, bp.fused_rounds != 0, st)
                              : launch_col(n, p->t_f64, 1, false, acc0, bp.tw_full, st);
             case LC_KERNEL_YX_INV:
                 return launch_yx_inv(n, acc0, p->scratch_real, false, bp.tw_half, bp.twist, bp.tw_full,

@@ -107,12 +107,18 @@ struct FusedArgs {
     void *part;              // second parts of split tiles: [band j][slot][N*CPW] complex
     int64_t part_stride;     // per band, >= max_parts * N * CPW
     int64_t max_parts;       // slots available in part (caps the persistent grid)
-    void *split_tab;         // int32 per tile: slot holding its second part, or -1
+    void *split_tab;         // int32 per tile: slot holding its second part, or -1 (written in
+                             // stream-K mode only; the rounds mode splits no tile)
     int32_t zero_dc;         // 1: drop the (0,0,0) bin (FP64 mean added later)
     int32_t kahan;           // 1: compensated sum
     int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
     int32_t parity;          // 1: spectra in the parity y layout of the half-plane xy shapes
+    // band means mu[band0 + j] = inv_n3 * sum_k g0[k B + band0 + j] sk[k] (the FP64
+    // DC mode), reduced by the first workgroup when mu is non-null
+    const double *sk = nullptr, *g0 = nullptr;
+    double inv_n3 = 0.0;
+    double *mu = nullptr;
 };
 int fused_variants(int n);   // number of register schedules compiled for n
 bool fused_parity_supported(int n);   // parity-layout input compiled for n
@@ -153,7 +159,8 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
 hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
                           bool lum_f64, int64_t n_cells, hipStream_t st);
-// sk[k] = sum_w dcpart[k*W + w];  mu[b] = sum_k g0[k*B + b] * sk[k] / n3
+// sk[k] = sum_w dcpart[k*W + w];  mu[b] = sum_k g0[k*B + b] * sk[k] / n3 (mu null:
+// the per-slice sums only; the fused z pass reduces mu, FusedArgs::mu)
 hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
                             double inv_n3, double *sk, double *mu, hipStream_t st);
 
