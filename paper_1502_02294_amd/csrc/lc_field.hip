@@ -764,20 +764,9 @@ __global__ __launch_bounds__(256) void dc_slice_kernel(const double *__restrict_
     if (threadIdx.x == 0) sk[k] = red[0];
 }
 
-__global__ __launch_bounds__(64) void dc_mu_kernel(const double *__restrict__ sk, int K,
-                                                   const double *__restrict__ g0, int B, double inv_n3,
-                                                   double *__restrict__ mu) {
-    for (int b = threadIdx.x; b < B; b += 64) {
-        double m = 0.0;
-        for (int k = 0; k < K; ++k) m += g0[(int64_t)k * B + b] * sk[k];
-        mu[b] = m * inv_n3;
-    }
-}
-
-hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
-                            double inv_n3, double *sk, double *mu, hipStream_t st) {
+hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, hipStream_t st) {
+    if (K < 1 || W < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(dc_slice_kernel, dim3(K), dim3(256), 0, st, dcpart, W, sk);
-    if (mu) hipLaunchKernelGGL(dc_mu_kernel, dim3(1), dim3(64), 0, st, sk, K, g0, B, inv_n3, mu);
     return hipGetLastError();
 }
 

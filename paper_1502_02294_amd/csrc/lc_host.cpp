@@ -835,7 +835,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
     hipStream_t st = p->stream;
     if (p->prec == LC_PREC_FP32) {
         // per-slice input sums; the fused z pass reduces the band means
-        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.ghat0, bp.B, inv_n3, bp.sk, nullptr, st));
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.sk, st));
         for (int b = b0; b < b1;) {
             const int nb = std::min(2, b1 - b);
             int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;

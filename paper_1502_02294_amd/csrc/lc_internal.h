@@ -159,9 +159,8 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
 hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
                           bool lum_f64, int64_t n_cells, hipStream_t st);
-// sk[k] = sum_w dcpart[k*W + w];  mu[b] = sum_k g0[k*B + b] * sk[k] / n3 (mu null:
-// the per-slice sums only; the fused z pass reduces mu, FusedArgs::mu)
-hipError_t launch_dc_reduce(const double *dcpart, int K, int W, const double *g0, int B,
-                            double inv_n3, double *sk, double *mu, hipStream_t st);
+// sk[k] = sum_w dcpart[k*W + w] (FP64 per-slice input sums; the fused z
+// pass forms the band means from them, FusedArgs::mu)
+hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, hipStream_t st);
 
 }  // namespace lc

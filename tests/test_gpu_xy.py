@@ -192,6 +192,35 @@ def test_autotune_two_sizes_one_step():
     plan.close()
 
 
+def test_autotune_picks_a_layout_at_256():
+    """At N = 256 the plan-time search compares the whole-plane and the
+    parity layout (forward, fused and inverse passes together); whichever it
+    keeps, the stepped field matches the oracle, and a second box of another
+    size in the same step is unaffected."""
+    lc = _lc()
+    boxes = [_box(256, K=4, seed=41), _box(128, K=3, seed=42)]
+    print("case autotune 256 + 128", flush=True)
+    plan = lc.Plan(boxes, precision=lc.LC_PREC_FP32, use_graph=True, autotune=True)
+    plan.build_all()
+    s0 = plan.get_schedule(0)
+    assert s0["n_xy"] == 7 and 0 <= s0["xy_variant"] < 7 and s0["push_group"] == 4
+    grids, outs = [], []
+    for b in boxes:
+        for c, v in b.sources:
+            grids.append(torch.from_numpy(li.dense_grid(b.n, c, v, np.float32)).cuda())
+        outs.append(torch.empty((b.n,) * 3, dtype=torch.float32, device="cuda"))
+    for _ in range(2):
+        plan.step(grids, outs)
+    torch.cuda.synchronize()
+    for b, o in zip(boxes, outs):
+        tg = _targets(b.n)
+        e_max, e_rms = oracle.rel_errors(o.double().cpu().numpy().ravel()[tg], _oracle(b, tg))
+        print(f"autotune n={b.n} schedule={plan.get_schedule(boxes.index(b))} e_max={e_max:.3e} e_rms={e_rms:.3e}",
+              flush=True)
+        assert e_rms <= 1e-5 and e_max <= 1e-4
+    plan.close()
+
+
 def test_schedule_validation():
     lc = _lc()
     box = _box(64, K=2)
