@@ -239,6 +239,7 @@ template <int N> static int x_wgs_t() {
 }
 
 int x_pass_wgs(int n) {
+    if (x_rows_supported(n)) return x_rows_wgs(n);   // the FP32 x pass there (the only one with DC partials)
     switch (n) {
 #define W_(N) case N: return x_wgs_t<N>();
         W_(8) W_(12) W_(16) W_(24) W_(32) W_(48) W_(64) W_(96) W_(128) W_(192) W_(256) W_(384) W_(512)
@@ -268,6 +269,8 @@ hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bo
                               int64_t spec_stride, const void *tw_half, const void *twist, double *dcpart,
                               hipStream_t st) {
     if (count < 1 || count > SrcTab::kMax) return hipErrorInvalidValue;
+    if (!t_f64 && x_rows_supported(n))
+        return launch_x_rows_batch(n, in, count, in_f64, spec, spec_stride, tw_half, twist, dcpart, st);
 #define X_(N)                                                                                          \
     if (t_f64) return in_f64 ? x_fwd_t<double, double, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st) \
                              : x_fwd_t<double, float, N>(in, count, spec, spec_stride, tw_half, twist, dcpart, st); \

@@ -51,6 +51,13 @@ hipError_t launch_x_fwd_batch(int n, bool t_f64, const SrcTab &in, int count, bo
 //   T[q] = E[q mod N/2] + W_N^q O[q mod N/2]
 // (completed by the fused z pass, FusedArgs::parity), and the plane sums go
 // to dcpart + i*dc_stride + 2z + s (2N per slice).
+// Forward x pass alone with an FP32 spectrum for N = 512 (x_rows_supported):
+// x_rows_wgs(n) workgroups per slice, each with one FP64 partial in dcpart
+// (dcpart + i*x_rows_wgs(n) for slice i); otherwise as launch_x_fwd_batch.
+bool x_rows_supported(int n);
+int x_rows_wgs(int n);
+hipError_t launch_x_rows_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
+                               const void *tw_half, const void *twist, double *dcpart, hipStream_t st);
 bool xy_supported(int n);
 int xy_variants(int n);
 bool xy_parity(int n, int variant);

@@ -499,6 +499,148 @@ hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const 
     return hipGetLastError();
 }
 
+// Forward x pass alone, FP32 spectrum, for N = 512 (a z-plane is too large
+// for one workgroup, so the y pass stays separate): the x phase of the fused
+// xy pass over RB batches of RPB rows per workgroup, two batches in flight
+// (one for FP64 input), the untangle done with lane moves, and each row's
+// half spectrum stored straight from registers (p = 0 and p = N/2 from the
+// packed element). With DC the FP64 sum of the workgroup's input goes to
+// dcpart + slice * wgs + workgroup.
+template <int N> struct XRowShape {
+    static constexpr int L = N / 2;
+    using SX = Sched<L>;
+    static constexpr int TX = SX::TPL;
+    static constexpr int NT = 256;
+    static constexpr int RPB = NT / TX;         // rows per batch
+    static constexpr int RB = 4;                // batches per workgroup
+    static constexpr int ROWS = RB * RPB;
+    static constexpr int SK = 4;
+    static constexpr int LSX = L + (L >> SK) + 1;
+};
+
+template <int N, typename TIN, bool DC>
+__global__ __launch_bounds__(XRowShape<N>::NT) void x_rows_kernel(SrcTab srcs, cx<float> *__restrict__ spec0,
+                                                                  int64_t spec_stride, int wgs,
+                                                                  const cx<float> *__restrict__ tw_half,
+                                                                  const cx<float> *__restrict__ twist,
+                                                                  double *__restrict__ dcpart0) {
+    using SH = XRowShape<N>;
+    constexpr int L = SH::L, TX = SH::TX, NT = SH::NT, RPB = SH::RPB, RB = SH::RB, SK = SH::SK, LSX = SH::LSX;
+    using EX = Engine<float, L, true, typename SH::SX, SK>;
+    constexpr int EXN = EX::E, RL = EX::RL, BPTL = EX::PLs::BPT, M = L / RL;
+    static_assert(BPTL * TX == M, "last x pass layout");
+    constexpr bool F32IN = std::is_same<TIN, float>::value;
+    constexpr int PF = F32IN ? 2 : 1;
+    __shared__ cx<float> lds[RPB * LSX];
+    __shared__ cx<float> twx[L], twt[L];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    const int xl = tid / TX, xt = tid % TX;
+    const bool t0 = xt == 0;
+    const int slice = blockIdx.x / wgs, blk = blockIdx.x % wgs;
+    const TIN *__restrict__ in = (const TIN *)srcs.p[slice];
+    cx<float> *__restrict__ mainp = spec0 + slice * spec_stride;
+    cx<float> *__restrict__ nyq = mainp + spec_main(N);
+    const int64_t row0 = (int64_t)blk * SH::ROWS;
+
+    cx<float> xr[RB][EXN];
+    auto load_batch = [&](auto bc, bool late) {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (b < RB) {
+            int64_t off = (row0 + b * RPB + xl) * N;
+            if (late) asm volatile("" : "+v"(off));   // keep the loads after the preceding barrier
+            const TIN *row = in + off;
+#pragma unroll
+            for (int e = 0; e < EXN; ++e) {
+                const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
+                xr[b][e] = mk((float)v.x, (float)v.y);
+            }
+        }
+    };
+    static_for<PF>([&](auto bc) { load_batch(bc, false); });
+    for (int i = tid; i < L; i += NT) {
+        twx[i] = tw_half[i];
+        const cx<float> w = twist[i];
+        twt[i] = mk(0.5f * w.y, -0.5f * w.x);   // V_q = -i W^q / 2
+    }
+    double dsum = 0.0;
+    static_for<RB>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        load_batch(std::integral_constant<int, b + PF>{}, true);
+        if constexpr (DC) {
+            if constexpr (F32IN) {
+#pragma unroll
+                for (int e = 0; e < EXN; ++e) dsum += (double)xr[b][e].x + (double)xr[b][e].y;
+            } else {
+                // FP64 input: sum the values before rounding (read again)
+                const TIN *row = in + (row0 + b * RPB + xl) * N;
+#pragma unroll
+                for (int e = 0; e < EXN; ++e) {
+                    const cx<TIN> v = *(const cx<TIN> *)(row + 2 * EX::in_pos(xt, e));
+                    dsum += (double)v.x + (double)v.y;
+                }
+            }
+            pin(dsum);
+        }
+        EX::run(xr[b], lds, xl * LSX, 1, xt, twx);
+        cx<float> pv[EXN];
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            const cx<float> sv = xr[b][partner_e<RL, BPTL>(e, false)];
+            const cx<float> o = mk(partner_val<TX>(sv.x), partner_val<TX>(sv.y));
+            pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
+        }
+        const int64_t row = row0 + b * RPB + xl;
+#pragma unroll
+        for (int e = 0; e < EXN; ++e) {
+            const int q = EX::out_pos(xt, e);
+            const cx<float> A = xr[b][e], B = pv[e];
+            if (e == 0 && t0) {
+                // q = 0: X[0] = Re A + Im A and X[N/2] = Re A - Im A, both real
+                mainp[row * L] = mk(A.x + A.y, 0.f);
+                nyq[row] = mk(A.x - A.y, 0.f);
+            } else {
+                const cx<float> S = mk(A.x + B.x, A.y - B.y), D = mk(A.x - B.x, A.y + B.y);
+                const cx<float> V = twt[q];
+                mainp[row * L + q] = mk(fmaf(0.5f, S.x, V.x * D.x - V.y * D.y), fmaf(0.5f, S.y, V.x * D.y + V.y * D.x));
+            }
+        }
+    });
+    if constexpr (DC) {
+        for (int o = 32; o > 0; o >>= 1) dsum += __shfl_down(dsum, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = dsum;
+        lds_barrier();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            dcpart0[(int64_t)slice * wgs + blk] = sum;
+        }
+    }
+}
+
+bool x_rows_supported(int n) { return n == 512; }
+int x_rows_wgs(int n) { return n == 512 ? (int)((int64_t)512 * 512 / XRowShape<512>::ROWS) : 0; }
+
+hipError_t launch_x_rows_batch(int n, const SrcTab &in, int count, bool in_f64, void *spec, int64_t spec_stride,
+                               const void *tw_half, const void *twist, double *dcpart, hipStream_t st) {
+    if (n != 512 || count < 1 || count > SrcTab::kMax) return hipErrorInvalidValue;
+    constexpr int N = 512;
+    using SH = XRowShape<N>;
+    const int wgs = x_rows_wgs(N);
+    const dim3 grid((unsigned)(wgs * count));
+#define XR_(TIN, DCF)                                                                                         \
+    hipLaunchKernelGGL((x_rows_kernel<N, TIN, DCF>), grid, dim3(SH::NT), 0, st, in, (cx<float> *)spec, spec_stride, \
+                       wgs, (const cx<float> *)tw_half, (const cx<float> *)twist, dcpart)
+    if (in_f64) {
+        if (dcpart) XR_(double, true); else XR_(double, false);
+    } else {
+        if (dcpart) XR_(float, true); else XR_(float, false);
+    }
+#undef XR_
+    return hipGetLastError();
+}
+
 bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
 
 // Launch shapes compiled per N (schedule, batches); the plan picks one.

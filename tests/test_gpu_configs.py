@@ -288,6 +288,38 @@ def test_time_kernel_reports_positive_durations():
     plan.close()
 
 
+def test_grid512_forward_x_pass_forms():
+    """N = 512 (the x pass alone, rows in batches with the untangle by lane
+    moves): FP32 and plain-FP32 forms, dense FP32 grids and FP64 point lists,
+    two slices, sampled cells against route D."""
+    lc = _lc()
+    n, K = 512, 2
+    L = 0.78125 * n
+    radii = np.linspace(0.0, 0.06 * L, K + 1)
+    srcs = [li.random_sources([512, k], n, 300) for k in range(K)]
+    box = li.Box(n=n, box=L, radii=radii, supersample=2, bands=[li.Atten(kind=0)], sources=srcs)
+    tg = li.sample_cells([512, 1], n, 1500)
+    Jr = oracle.field_direct_ondemand(n, L, radii, 2, box.bands[0], srcs, tg)
+    for prec in (lc.LC_PREC_FP32, lc.LC_PREC_FP32_PLAIN):
+        plan = lc.Plan([box], precision=prec)
+        plan.build_all()
+        for dense in (True, False):
+            print(f"case n=512 prec={prec} dense={dense}", flush=True)
+            if dense:
+                keep = [plan.push_grid(0, k, torch.from_numpy(li.dense_grid(n, c, v, np.float32)).cuda())
+                        for k, (c, v) in enumerate(srcs)]
+            else:
+                keep = [plan.push_points(0, k, torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
+                        for k, (c, v) in enumerate(srcs)]
+            J = plan.field(0, 0).double().cpu().numpy().ravel()
+            torch.cuda.synchronize()
+            del keep
+            e_max, e_rms = oracle.rel_errors(J[tg], Jr)
+            print(f"n=512 prec={prec} dense={dense} e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+            assert e_rms <= 1e-5 and e_max <= 1e-4
+        plan.close()
+
+
 def test_grid384_sampled_fp64_and_fp32():
     """N = 384 (radix 3 in every pass; eight-element fused schedule with
     8-column tiles): two slices, sampled cells against route D."""
