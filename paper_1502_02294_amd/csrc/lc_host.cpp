@@ -258,6 +258,17 @@ struct lc_plan_s {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<uint8_t> gkey;
+    // side streams (default priority, created by the plan) on which lc_step
+    // runs the boxes of a multi-box plan concurrently, forked from and joined
+    // back to the plan's stream with events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t fork = nullptr;
+    ~lc_plan_s() {
+        for (hipEvent_t e : side_done) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipStream_t t : side) (void)hipStreamDestroy(t);
+    }
 };
 
 namespace {
@@ -689,6 +700,17 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             done_bp.push_back(&bp);
         }
     }
+    // up to three side streams for concurrent boxes in lc_step (four lanes)
+    const int nside = std::min<int>(3, (int)p->boxes.size() - 1);
+    for (int i = 0; i < nside; ++i) {
+        hipStream_t t = nullptr;
+        hipEvent_t e = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        p->side.push_back(t);
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->side_done.push_back(e);
+    }
+    if (nside > 0) HIPCHK(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(p->stream));
     *out = p.release();
     return ok();
@@ -826,13 +848,12 @@ int lc_push_sources(lc_plan_t *p, int32_t box, int32_t slice, const lc_sources *
 }
 
 // Field of one box for bands [b0, b1) into device pointers outp[b - b0].
-static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64) {
+static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64, hipStream_t st) {
     BoxPlan &bp = p->boxes[box];
     const int n = bp.n, K = bp.K;
     const size_t cs = p->t_f64 ? 16 : 8;
     const int64_t se = spec_elems(n);
     const double inv_n3 = 1.0 / ((double)n * n * n);
-    hipStream_t st = p->stream;
     if (p->prec == LC_PREC_FP32) {
         // per-slice input sums; the fused z pass reduces the band means
         HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.sk, st));
@@ -910,13 +931,13 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
         BoxPlan &bp = p->boxes[x];
         const int b0 = band < 0 ? 0 : band, b1 = band < 0 ? bp.B : band + 1;
         if (mem == LC_MEM_DEVICE) {
-            int rc = field_box(p, x, b0, b1, out + o, f64);
+            int rc = field_box(p, x, b0, b1, out + o, f64, p->stream);
             if (rc) return rc;
         } else {
             const size_t bytes = (size_t)bp.n * bp.n * bp.n * (f64 ? 8 : 4);
             for (int b = b0; b < b1; ++b) {
                 void *dev = p->scratch_real;
-                int rc = field_box(p, x, b, b + 1, &dev, f64);
+                int rc = field_box(p, x, b, b + 1, &dev, f64, p->stream);
                 if (rc) return rc;
                 HIPCHK(hipMemcpyAsync(out[o + (b - b0)], dev, bytes, hipMemcpyDeviceToHost, p->stream));
                 HIPCHK(hipStreamSynchronize(p->stream));
@@ -927,57 +948,98 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
     return ok();
 }
 
-static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtype) {
-    size_t si = 0, oi = 0;
+// One box of lc_step on stream st: its slices' forward passes (groups of up
+// to push_group consecutive dense slices of one value type per batched
+// launch; point lists one by one, through the plan's staging grid, on the
+// plan's stream only) and its field.
+static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *out, int32_t dtype, hipStream_t st) {
     const size_t cs = p->t_f64 ? 16 : 8;
-    for (int x = 0; x < (int)p->boxes.size(); ++x) {
-        BoxPlan &bp = p->boxes[x];
-        const int n = bp.n;
-        const int64_t se = spec_elems(n);
-        // groups of up to push_group consecutive dense slices of one value
-        // type go through one batched x pass and one batched y pass (z too
-        // for unfused forms); small groups keep each slice's spectrum in the
-        // last-level cache between its x and y passes
-        int k = 0;
-        while (k < bp.K) {
-            const lc_sources &s0 = srcs[si + k];
-            if (s0.kind != 0) {
-                int rc = push_impl(p, x, k, &s0);
-                if (rc) return rc;
-                ++k;
-                continue;
-            }
-            int cnt = 0;
-            SrcTab tab;
-            while (k + cnt < bp.K && cnt < bp.push_group && srcs[si + k + cnt].kind == 0 &&
-                   srcs[si + k + cnt].dtype == s0.dtype) {
-                tab.p[cnt] = srcs[si + k + cnt].grid;
-                bp.last_src[k + cnt] = srcs[si + k + cnt].grid;
-                bp.last_src_f64[k + cnt] = s0.dtype == LC_F64 ? 1 : 0;
-                ++cnt;
-            }
-            char *spec = bp.spec + (size_t)k * se * cs;
-            double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.dcw : nullptr;
-            if (bp.use_xy) {
-                HIPCHK(launch_xy_fwd_batch(n, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist,
-                                           bp.tw_full, dcp, bp.dcw, bp.xy_variant, p->stream));
-            } else {
-                HIPCHK(launch_x_fwd_batch(n, p->t_f64, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half,
-                                          bp.twist, dcp, p->stream));
-                HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, p->stream));
-            }
-            if (p->prec != LC_PREC_FP32)
-                HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, p->stream));
-            for (int j = 0; j < cnt; ++j) bp.pushed[k + j] = 1;
-            k += cnt;
+    BoxPlan &bp = p->boxes[x];
+    const int n = bp.n;
+    const int64_t se = spec_elems(n);
+    int k = 0;
+    while (k < bp.K) {
+        const lc_sources &s0 = srcs[k];
+        if (s0.kind != 0) {
+            int rc = push_impl(p, x, k, &s0);
+            if (rc) return rc;
+            ++k;
+            continue;
         }
-        si += bp.K;
+        int cnt = 0;
+        SrcTab tab;
+        while (k + cnt < bp.K && cnt < bp.push_group && srcs[k + cnt].kind == 0 && srcs[k + cnt].dtype == s0.dtype) {
+            tab.p[cnt] = srcs[k + cnt].grid;
+            bp.last_src[k + cnt] = srcs[k + cnt].grid;
+            bp.last_src_f64[k + cnt] = s0.dtype == LC_F64 ? 1 : 0;
+            ++cnt;
+        }
+        char *spec = bp.spec + (size_t)k * se * cs;
+        double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.dcw : nullptr;
+        if (bp.use_xy) {
+            HIPCHK(launch_xy_fwd_batch(n, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist, bp.tw_full,
+                                       dcp, bp.dcw, bp.xy_variant, st));
+        } else {
+            HIPCHK(launch_x_fwd_batch(n, p->t_f64, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist,
+                                      dcp, st));
+            HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, st));
+        }
+        if (p->prec != LC_PREC_FP32) HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
+        for (int j = 0; j < cnt; ++j) bp.pushed[k + j] = 1;
+        k += cnt;
     }
-    for (int x = 0; x < (int)p->boxes.size(); ++x) {
-        BoxPlan &bp = p->boxes[x];
-        int rc = field_box(p, x, 0, bp.B, out + oi, dtype == LC_F64);
+    return field_box(p, x, 0, bp.B, out, dtype == LC_F64, st);
+}
+
+// lc_step's work. With dense sources only and several boxes, the boxes run
+// concurrently on up to four lanes (the plan's stream and its side
+// streams): each box's work stays on one lane and touches only that box's
+// part of the workspace, its sources and its outputs. The boxes go to the
+// lanes largest first (N^3 K), each to the least loaded lane.
+static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtype) {
+    const int nb = (int)p->boxes.size();
+    std::vector<size_t> si(nb), oi(nb);
+    bool dense = true;
+    {
+        size_t a = 0, o = 0;
+        for (int x = 0; x < nb; ++x) {
+            si[x] = a;
+            oi[x] = o;
+            for (int k = 0; k < p->boxes[x].K; ++k) dense = dense && srcs[a + k].kind == 0;
+            a += p->boxes[x].K;
+            o += p->boxes[x].B;
+        }
+    }
+    if (!dense || p->side.empty()) {
+        for (int x = 0; x < nb; ++x) {
+            int rc = step_box(p, x, srcs + si[x], out + oi[x], dtype, p->stream);
+            if (rc) return rc;
+        }
+        return LC_OK;
+    }
+    const int nl = (int)p->side.size() + 1;
+    std::vector<int> order(nb), lane(nb);
+    for (int x = 0; x < nb; ++x) order[x] = x;
+    auto work = [&](int x) { return (double)p->boxes[x].n * p->boxes[x].n * p->boxes[x].n * p->boxes[x].K; };
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return work(u) > work(v); });
+    std::vector<double> load(nl, 0.0);
+    for (int x : order) {
+        int best = 0;
+        for (int l = 1; l < nl; ++l)
+            if (load[l] < load[best]) best = l;
+        lane[x] = best;
+        load[best] += work(x);
+    }
+    HIPCHK(hipEventRecord(p->fork, p->stream));
+    for (hipStream_t t : p->side) HIPCHK(hipStreamWaitEvent(t, p->fork, 0));
+    for (int x : order) {
+        hipStream_t st = lane[x] == 0 ? p->stream : p->side[lane[x] - 1];
+        int rc = step_box(p, x, srcs + si[x], out + oi[x], dtype, st);
         if (rc) return rc;
-        oi += bp.B;
+    }
+    for (size_t i = 0; i < p->side.size(); ++i) {
+        HIPCHK(hipEventRecord(p->side_done[i], p->side[i]));
+        HIPCHK(hipStreamWaitEvent(p->stream, p->side_done[i], 0));
     }
     return LC_OK;
 }
