@@ -153,7 +153,9 @@ size_t lc_workspace_bytes(const lc_plan_desc *desc);
  * Errors: LC_EINVAL (bad field), LC_EUNSUPPORTED (N not 2^a 3^b in
  * 8..1024, m > 8, or r_0 = 0 with r_1 < (sqrt(3)/2) l so that the self
  * cell would straddle two slices), LC_ENOMEM (workspace too small or
- * misaligned to 256 bytes), LC_EDEVICE (no gfx950 device). */
+ * misaligned to 256 bytes), LC_EDEVICE (no gfx950 device). A plan of
+ * several boxes also creates up to three side streams (default priority) on
+ * the current device for lc_step; lc_destroy releases them. */
 int lc_plan(const lc_plan_desc *desc, lc_plan_t **out);
 
 /* Build G_{k,b} for all K slices of one (box, band) - algorithm steps 2-3:
@@ -183,10 +185,15 @@ int lc_field(lc_plan_t *plan, int32_t box, int32_t band, void *const *out,
  * sum_b K_b entries, device memory only) and evaluate every band into out
  * (box-major, band, device memory). With use_graph = 1 the launch sequence
  * is captured in a HIP graph on first use and replayed while the argument
- * pointers are unchanged. */
+ * pointers are unchanged. With dense sources only, the boxes of a
+ * multi-box plan run concurrently on the plan's stream and its side
+ * streams, forked from and joined back to the plan's stream: as for every
+ * call, the work is complete when the plan's stream reaches the end of the
+ * call. Outputs of different boxes must not overlap. */
 int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t dtype);
 
-/* Release the plan's host state (no caller memory is freed). NULL is a no-op. */
+/* Release the plan's host state and its side streams (no caller memory is
+ * freed). NULL is a no-op. */
 void lc_destroy(lc_plan_t *plan);
 
 /* Text of the last error on the calling thread; valid until the next
