@@ -304,6 +304,30 @@ __device__ __forceinline__ void run_passes_db(cx<T> *la, cx<T> *lb, int lbase, i
     }
 }
 
+// The same passes for two lines at once, line i alternating between its own
+// buffers la_i and lb_i; one barrier after both lines' writes serves both.
+template <typename T, int L, bool FWD, int P, int PEND, typename S, int SK>
+__device__ __forceinline__ void run_passes2_db(cx<T> *la0, cx<T> *lb0, cx<T> *la1, cx<T> *lb1, int lbase, int es,
+                                               int t, const cx<T> *tw) {
+    if constexpr (P < PEND) {
+        constexpr int R = pass_radix<L, FWD, S>(P);
+        constexpr int NS = ns_before<L, FWD, S>(P);
+        using PS = Pass<T, L, R, NS, S::TPL, FWD, SK>;
+        {
+            cx<T> v[PS::BPT][R];
+            PS::read(((P - 1) & 1) ? lb0 : la0, lbase, es, t, tw, v);
+            PS::write((P & 1) ? lb0 : la0, lbase, es, t, v);
+        }
+        {
+            cx<T> v[PS::BPT][R];
+            PS::read(((P - 1) & 1) ? lb1 : la1, lbase, es, t, tw, v);
+            PS::write((P & 1) ? lb1 : la1, lbase, es, t, v);
+        }
+        lds_barrier();
+        run_passes2_db<T, L, FWD, P + 1, PEND, S, SK>(la0, lb0, la1, lb1, lbase, es, t, tw);
+    }
+}
+
 // Register-in / register-out transform of one line by TPL threads.
 // x[e] (e < E) holds, on entry, the first pass's inputs at line positions
 // in_pos(t, e) and, on return, the last pass's outputs at out_pos(t, e).
@@ -412,6 +436,55 @@ struct Engine {
         rest_db(x, y, la, lb, lbase, es, t, tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = y[e];
+    }
+
+    // Two lines through the transform with their exchanges interleaved: line
+    // i alternates between its own buffers la_i and lb_i, and each barrier
+    // serves both lines (half the barriers of two run_db calls). first2_db
+    // takes the first-pass inputs (x0, x1 are free on return); rest2_db calls
+    // mid() right after its first barrier, when every thread has finished
+    // the previous rest2_db, and then out(i, y) with the outputs of line i
+    // (line 0 first, so that only one line's outputs are live at a time).
+    // A sequence of these calls by the same threads needs no other barrier.
+    __device__ __forceinline__ static void first2_db(cx<T> (&x0)[E], cx<T> (&x1)[E], cx<T> *la0, cx<T> *la1,
+                                                     int lbase, int es, int t) {
+        static_assert(NP > 1, "the interleaved form exchanges through LDS");
+#pragma unroll
+        for (int i = 0; i < P0::BPT; ++i) dft<R0, FWD>(x0 + i * R0);
+#pragma unroll
+        for (int i = 0; i < P0::BPT; ++i) dft<R0, FWD>(x1 + i * R0);
+        if constexpr ((NP - 1) % 2 == 1) lds_barrier();
+#pragma unroll
+        for (int i = 0; i < P0::BPT; ++i) {
+            const int o = (t + i * TPL) * R0;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                la0[lbase + lpos<SK>(o + r) * es] = x0[i * R0 + r];
+                la1[lbase + lpos<SK>(o + r) * es] = x1[i * R0 + r];
+            }
+        }
+    }
+    template <typename M, typename F>
+    __device__ __forceinline__ static void rest2_db(cx<T> *la0, cx<T> *lb0, cx<T> *la1, cx<T> *lb1, int lbase,
+                                                    int es, int t, const cx<T> *tw, M &&mid, F &&out) {
+        lds_barrier();
+        mid();
+        run_passes2_db<T, L, FWD, 1, NP - 1, S, SK>(la0, lb0, la1, lb1, lbase, es, t, tw);
+        constexpr bool B = ((NP - 2) & 1) != 0;
+#pragma unroll
+        for (int li = 0; li < 2; ++li) {
+            const cx<T> *src = li == 0 ? (B ? lb0 : la0) : (B ? lb1 : la1);
+            cx<T> y[E];
+#pragma unroll
+            for (int i = 0; i < PLs::BPT; ++i) {
+                const int b = t + i * TPL;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) y[i * RL + r] = src[lbase + lpos<SK>(b + r * PLs::NB) * es];
+                PLs::twiddle(y + i * RL, b, tw);
+                dft<RL, FWD>(y + i * RL);
+            }
+            out(li, y);
+        }
     }
 };
 

@@ -150,13 +150,22 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     constexpr int RSTEP = NT / CPW;                        // = threads per column
     constexpr int GROWS = (HP + RSTEP - 1) / RSTEP;        // octant rows loaded per thread
     constexpr int NO = PAR ? 2 : 1;                        // output columns per input column
+    // pair tiles of one band: the two outputs' transforms run interleaved
+    // (Engine::first2_db / rest2_db), two barriers per slice instead of four
+    constexpr bool IL = PAR && NB_ == 1 && EF::NP > 1;
     // z transform line buffers, alternated by exchange (Engine::run_db):
-    // only the barriers after the writes remain in the slice loop
+    // only the barriers after the writes remain in the slice loop; lds3 and
+    // lds4 are the second output's pair in the interleaved form
     __shared__ cx<float> lds[L * ES], lds2[L * ES];
+    __shared__ cx<float> lds3[IL ? L * ES : 1], lds4[IL ? L * ES : 1];
     __shared__ cx<float> tws[L];
-    // kernel octant rows of the tile (all folded z frequencies), per output,
-    // double buffered by slice: rows r and L-r of a column share one entry
-    __shared__ float gl[2][NB_ * NO][HP * CPW];
+    // kernel octant rows of the tile (all folded z frequencies), per output:
+    // rows r and L-r of a column share one entry. Double buffered by slice;
+    // one buffer in the interleaved form, which stores slice k's rows after
+    // the first barrier of slice k (every reader of slice k-1's rows has
+    // passed it) and reads them after the second.
+    constexpr int GB = IL ? 1 : 2;
+    __shared__ float gl[GB][NB_ * NO][HP * CPW];
     for (int i = threadIdx.x; i < L; i += NT) tws[i] = tw_g[i];
     // the FP64 band means (DC mode), once per launch, by the first wave of
     // workgroup 0: mu_b = inv_n3 sum_k G^_{k,b}(0) S^_k(0)
@@ -298,7 +307,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // octant rows of slice k go to LDS buffer k&1, whose previous
         // contents (slice k-2) were last read before the barriers of slice k-1
         auto store_g = [&](int k) {
-            float *glk = &gl[k & 1][0][0];
+            float *glk = &gl[(k & 1) % GB][0][0];
 #pragma unroll
             for (int b = 0; b < NB_; ++b)
 #pragma unroll
@@ -325,15 +334,11 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                 }
         };
         load_g(k0);
-        store_g(k0);
-        for (int kk = k0; kk < kend; kk += PF) {
+        if constexpr (IL) {
+            for (int kk = k0; kk < kend; kk += PF) {
 #pragma unroll
-            for (int j = 0; j < PF; ++j) {
-                const int k = kk + j;
-                const float *glk = &gl[k & 1][0][0];
-                // the next slice's octant rows are in flight during this slice
-                load_g(k + 1);
-                if constexpr (PAR) {
+                for (int j = 0; j < PF; ++j) {
+                    const int k = kk + j;
                     // last radix-2 step of the y transform: E +- W_N^q O
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
@@ -342,32 +347,65 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                         xb[j][e] = mk(x.x + ux, x.y + uy);
                         ob[j][e] = mk(x.x - ux, x.y - uy);
                     }
+                    EF::first2_db(xb[j], ob[j], lds, lds3, c, ES, t);
+                    // buffer j is free: refill it with slice k + PF
+                    fill(j, k + PF);
+                    EF::rest2_db(
+                        lds, lds2, lds3, lds4, c, ES, t, tws,
+                        [&] {
+                            // slice k's octant rows (loaded during slice k - 1),
+                            // then slice k + 1's in flight
+                            store_g(k);
+                            load_g(k + 1);
+                        },
+                        [&](int o, const cx<float>(&v)[E]) { mac(o, &gl[0][0][0], v); });
                 }
-                EF::first_db(xb[j], lds, c, ES, t);
-                cx<float> v[E];
-                if constexpr (EF::NP == 1) {
+            }
+        } else {
+            store_g(k0);
+            for (int kk = k0; kk < kend; kk += PF) {
 #pragma unroll
-                    for (int e = 0; e < E; ++e) v[e] = xb[j][e];
-                    lds_barrier();    // kernel values in LDS visible
-                }
-                // buffer j is free (both halves once the second output has
-                // entered its transform): refill it with slice k + PF
-                if constexpr (!PAR) fill(j, k + PF);
-                if constexpr (EF::NP > 1) EF::rest_db(xb[j], v, lds, lds2, c, ES, t, tws);
-                mac(0, glk, v);
-                if constexpr (PAR) {
-                    EF::first_db(ob[j], lds, c, ES, t);
+                for (int j = 0; j < PF; ++j) {
+                    const int k = kk + j;
+                    const float *glk = &gl[k & 1][0][0];
+                    // the next slice's octant rows are in flight during this slice
+                    load_g(k + 1);
+                    if constexpr (PAR) {
+                        // last radix-2 step of the y transform: E +- W_N^q O
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const cx<float> x = xb[j][e], y = ob[j][e];
+                            const float ux = fmaf(wq.x, y.x, -wq.y * y.y), uy = fmaf(wq.x, y.y, wq.y * y.x);
+                            xb[j][e] = mk(x.x + ux, x.y + uy);
+                            ob[j][e] = mk(x.x - ux, x.y - uy);
+                        }
+                    }
+                    EF::first_db(xb[j], lds, c, ES, t);
+                    cx<float> v[E];
                     if constexpr (EF::NP == 1) {
 #pragma unroll
-                        for (int e = 0; e < E; ++e) v[e] = ob[j][e];
+                        for (int e = 0; e < E; ++e) v[e] = xb[j][e];
+                        lds_barrier();    // kernel values in LDS visible
                     }
-                    fill(j, k + PF);
-                    if constexpr (EF::NP > 1) EF::rest_db(ob[j], v, lds, lds2, c, ES, t, tws);
-                    mac(1, glk, v);
+                    // buffer j is free (both halves once the second output has
+                    // entered its transform): refill it with slice k + PF
+                    if constexpr (!PAR) fill(j, k + PF);
+                    if constexpr (EF::NP > 1) EF::rest_db(xb[j], v, lds, lds2, c, ES, t, tws);
+                    mac(0, glk, v);
+                    if constexpr (PAR) {
+                        EF::first_db(ob[j], lds, c, ES, t);
+                        if constexpr (EF::NP == 1) {
+#pragma unroll
+                            for (int e = 0; e < E; ++e) v[e] = ob[j][e];
+                        }
+                        fill(j, k + PF);
+                        if constexpr (EF::NP > 1) EF::rest_db(ob[j], v, lds, lds2, c, ES, t, tws);
+                        mac(1, glk, v);
+                    }
+                    // stored at the end of the slice, after the refill loads were
+                    // issued, so that waiting for them does not wait for the refill
+                    store_g(k + 1);
                 }
-                // stored at the end of the slice, after the refill loads were
-                // issued, so that waiting for them does not wait for the refill
-                store_g(k + 1);
             }
         }
 
