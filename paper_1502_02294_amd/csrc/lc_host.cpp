@@ -681,7 +681,9 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         p->boxes.push_back(std::move(bp));
     }
     if (d->autotune && p->prec == LC_PREC_FP32) {
-        // boxes of equal N share the shapes measured on the first of them
+        // boxes of equal N share the shapes measured on the first of them;
+        // the slices per forward launch follow each box's own slice count,
+        // as the tuner would set them (all slices, up to the table size)
         std::vector<int> done_n;
         std::vector<const BoxPlan *> done_bp;
         for (auto &bp : p->boxes) {
@@ -689,7 +691,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             while (j < done_n.size() && done_n[j] != bp.n) ++j;
             if (j < done_n.size()) {
                 bp.xy_variant = done_bp[j]->xy_variant;
-                bp.push_group = done_bp[j]->push_group;
+                bp.push_group = std::min(bp.K, SrcTab::kMax);
                 bp.fused_variant = done_bp[j]->fused_variant;
                 bp.fused_rounds = done_bp[j]->fused_rounds;
                 bp.dcw = bp.dc_width();
