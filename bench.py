@@ -94,17 +94,21 @@ def run_form(lc, torch, box, grids, precision, steps, warmup, time_kernels=True)
     t_build = time.perf_counter() - t0
     odt = torch.float64 if precision == lc.LC_PREC_FP64 else torch.float32
     outs = [torch.empty((n, n, n), dtype=odt, device="cuda") for _ in range(B)]
-    for _ in range(max(1, warmup)):
-        plan.step(grids, outs)
-    torch.cuda.synchronize()
     st = plan.stream          # the stream the kernels run on
+    # steps are issued with the plan's stream current, as a loop of steps
+    # would run in production: no cross-stream ordering between steps
+    with torch.cuda.stream(st):
+        for _ in range(max(1, warmup)):
+            plan.step(grids, outs)
+    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
-    e0.record(st)
-    for _ in range(steps):
-        plan.step(grids, outs)
-    e1.record(st)
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            plan.step(grids, outs)
+        e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1) / steps

@@ -219,11 +219,20 @@ class Plan:
         self.handle = lc_plan(desc)
         self._leave()
 
+    # Order the plan's stream after torch's current stream on entry, and the
+    # current stream after the plan's work on exit. With the plan's stream
+    # current (torch.cuda.stream(plan.stream)) both are skipped, so that
+    # consecutive calls start without a cross-stream round trip; the caller
+    # then orders the plan's stream against its other streams itself.
     def _enter(self):
-        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
 
     def _leave(self):
-        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def build_greens(self, box: int = 0, band: int = 0, atten=None):
         at = atten if atten is not None else self.boxes[box].bands[band]

@@ -223,6 +223,37 @@ def test_autotune_two_sizes_one_step():
     plan.close()
 
 
+def test_step_with_the_plans_stream_current():
+    """Steps issued with the plan's stream as torch's current stream (no
+    cross-stream ordering in the binding: the caller orders the plan's stream
+    against its other streams) give the same field bit for bit as steps
+    issued from torch's default stream."""
+    lc = _lc()
+    boxes = [_box(64, K=3, seed=51), _box(96, K=2, seed=52)]
+    print("case plan stream current", flush=True)
+    plan = lc.Plan(boxes, precision=lc.LC_PREC_FP32, use_graph=True)
+    plan.build_all()
+    grids, outs = [], []
+    for b in boxes:
+        for c, v in b.sources:
+            grids.append(torch.from_numpy(li.dense_grid(b.n, c, v, np.float32)).cuda())
+        outs.append(torch.empty((b.n,) * 3, dtype=torch.float32, device="cuda"))
+    plan.step(grids, outs)
+    ref = [o.clone() for o in outs]
+    for o in outs:
+        o.fill_(float("nan"))
+    # the caller's ordering: the plan's stream after the fill, and the
+    # default stream after the steps
+    plan.stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(plan.stream):
+        for _ in range(3):
+            plan.step(grids, outs)
+    torch.cuda.current_stream().wait_stream(plan.stream)
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+    plan.close()
+
+
 def test_autotune_picks_a_layout_at_256():
     """At N = 256 the plan-time search compares the whole-plane and the
     parity layout (forward, fused and inverse passes together); whichever it
