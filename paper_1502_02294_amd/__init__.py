@@ -320,18 +320,29 @@ class Plan:
         self._leave()
 
     def step(self, grids, outs, dtype=None):
-        """One whole step (lc_step): push every slice of every box from dense
-        device grids (box-major list) and evaluate every band into outs
-        (box-major, band; device tensors of one dtype)."""
+        """One whole step (lc_step): push every slice of every box (box-major
+        list of device sources: a dense grid tensor, or a point list given as
+        a (cells, lum) pair of tensors) and evaluate every band into outs
+        (box-major, band; device tensors of one dtype). Returns the point-list
+        tensors passed on (contiguous copies where needed), which must stay
+        alive until the stream has run the step."""
         torch = self.torch
-        srcs = []
+        srcs, keep = [], []
         for g in grids:
-            dt = LC_F64 if g.dtype == torch.float64 else LC_F32
-            srcs.append(lc_sources(0, dt, LC_MEM_DEVICE, 0, g.data_ptr(), 0, None, None))
+            if isinstance(g, (tuple, list)):
+                c, v = g[0].contiguous(), g[1].contiguous()
+                dt = LC_F64 if v.dtype == torch.float64 else LC_F32
+                srcs.append(lc_sources(1, dt, LC_MEM_DEVICE, 0, None, int(c.numel()),
+                                       c.data_ptr() if c.numel() else None, v.data_ptr() if v.numel() else None))
+                keep.append((c, v))
+            else:
+                dt = LC_F64 if g.dtype == torch.float64 else LC_F32
+                srcs.append(lc_sources(0, dt, LC_MEM_DEVICE, 0, g.data_ptr(), 0, None, None))
         odt = LC_F64 if outs[0].dtype == torch.float64 else LC_F32
         self._enter()
         lc_step(self.handle, srcs, [o.data_ptr() for o in outs], odt)
         self._leave()
+        return keep
 
     def close(self):
         if getattr(self, "handle", None):

@@ -254,6 +254,55 @@ def test_step_with_the_plans_stream_current():
     plan.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_step_with_point_lists_among_dense_grids(form):
+    """lc_step with device point lists among the dense grids (every other
+    slice over two boxes): the point lists go through the plan's staging grid,
+    so the boxes run in order on the plan's stream, captured in a graph. The
+    field equals the step of the same sources as dense grids, on two replays
+    (the point lists are deposited with FP64 atomics, so coincident sources
+    may add in another order)."""
+    lc = _lc()
+    prec = lc.LC_PREC_FP64 if form == "fp64" else lc.LC_PREC_FP32
+    dt = torch.float64 if form == "fp64" else torch.float32
+    tol = 1e-12 if form == "fp64" else 1e-5
+    boxes = [_box(64, K=3, seed=61), _box(96, K=2, seed=62)]
+    dense, mixed = [], []
+    i = 0
+    for b in boxes:
+        for cells, lum in b.sources:
+            g = torch.from_numpy(li.dense_grid(b.n, cells, lum, np.float64)).to(dt).cuda()
+            dense.append(g)
+            if i % 2 == 1:
+                mixed.append((torch.from_numpy(np.asarray(cells, np.int64)).cuda(),
+                              torch.from_numpy(np.asarray(lum, np.float64)).to(dt).cuda()))
+            else:
+                mixed.append(g)
+            i += 1
+    print(f"case step with point lists {form}", flush=True)
+    ref = [torch.empty((b.n,) * 3, dtype=dt, device="cuda") for b in boxes]
+    plan = lc.Plan(boxes, precision=prec, use_graph=True)
+    plan.build_all()
+    plan.step(dense, ref)
+    torch.cuda.synchronize()
+    plan.close()
+    plan = lc.Plan(boxes, precision=prec, use_graph=True)
+    plan.build_all()
+    outs = [torch.empty((b.n,) * 3, dtype=dt, device="cuda") for b in boxes]
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        keep = plan.step(mixed, outs)
+        torch.cuda.synchronize()
+        assert len(keep) == 2
+        for o, r in zip(outs, ref):
+            d = float((o.double() - r.double()).abs().max())
+            sc = float(r.double().abs().max())
+            print(f"  replay {rep} n={o.shape[0]} max diff / max = {d / sc:.3e}", flush=True)
+            assert d <= tol * sc
+    plan.close()
+
+
 def test_autotune_picks_a_layout_at_256():
     """At N = 256 the plan-time search compares the whole-plane and the
     parity layout (forward, fused and inverse passes together); whichever it
