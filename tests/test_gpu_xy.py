@@ -303,6 +303,35 @@ def test_step_with_point_lists_among_dense_grids(form):
     plan.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_step_with_mixed_grid_dtypes(form):
+    """Dense grids of both value types in one box (FP32, FP32, FP64, FP32):
+    lc_step groups consecutive slices of one type per forward launch, so the
+    FP64 slice splits the groups. With FP32-representable values the field
+    equals the step of the same values as grids of one type."""
+    lc = _lc()
+    prec = lc.LC_PREC_FP64 if form == "fp64" else lc.LC_PREC_FP32
+    odt = torch.float64 if form == "fp64" else torch.float32
+    tol = 1e-12 if form == "fp64" else 1e-6
+    box = _box(64, K=4, seed=71)
+    g32 = [torch.from_numpy(li.dense_grid(box.n, c, v, np.float32)).cuda() for c, v in box.sources]
+    mixed = [g32[0], g32[1], g32[2].double(), g32[3]]
+    same = g32 if form == "fp32" else [g.double() for g in g32]
+    print(f"case mixed grid dtypes {form}", flush=True)
+    plan = lc.Plan([box], precision=prec, use_graph=True)
+    plan.build_all()
+    ref = [torch.empty((box.n,) * 3, dtype=odt, device="cuda")]
+    out = [torch.empty((box.n,) * 3, dtype=odt, device="cuda")]
+    plan.step(same, ref)
+    plan.step(mixed, out)
+    torch.cuda.synchronize()
+    d = float((out[0].double() - ref[0].double()).abs().max())
+    sc = float(ref[0].double().abs().max())
+    print(f"  max diff / max = {d / sc:.3e}", flush=True)
+    assert d <= tol * sc
+    plan.close()
+
+
 def test_autotune_picks_a_layout_at_256():
     """At N = 256 the plan-time search compares the whole-plane and the
     parity layout (forward, fused and inverse passes together); whichever it
