@@ -2,9 +2,15 @@
 
 This module only draws random inputs: box geometry, slice radii, attenuation
 parameters and per-slice point-source lists (flat cell index, luminosity).
-It holds none of the method's arithmetic (no shell kernel, no deposit, no
-transform), so both the CPU oracle and the HIP library consume exactly the
+It holds none of the method's arithmetic (no shell kernel, no transform, no
+slice sum), so both the CPU oracle and the HIP library consume exactly the
 same inputs from here and share nothing else.
+
+One input format conversion lives here: `dense_grid` writes a point list as
+a per-cell luminosity grid (coincident sources add), the input format of a
+simulation that keeps its sources on the mesh. It feeds the library's
+dense-grid entry only; the oracle's own grids come from `oracle.deposit`,
+and its direct-summation routes take the point lists themselves.
 
 The paper's own source fields (first-star luminosities from a reionization
 simulation, Sec. 3) are not available; these recipes stand in for them with
@@ -88,15 +94,16 @@ def poisson_sources(rng: np.random.Generator, n: int, density: float):
     return cells, lum.astype(np.float64)
 
 
-def grf_peak_sources(rng: np.random.Generator, n: int, frac: float = 0.01):
+def grf_peak_sources(rng: np.random.Generator, n: int, frac: float = 0.01, workers: int = -1):
     """Top `frac` of cells of a Gaussian random field with P(k) ~ k^-2.
 
     White noise is filtered by |k|^-1 in Fourier space (k=0 mode zeroed).
     Luminosity is the excess of the field over the first rejected value.
+    (scipy's transforms give the same bits for any `workers`.)
     """
     import scipy.fft as sfft
     white = rng.standard_normal((n, n, n))
-    wk = sfft.rfftn(white, workers=-1)
+    wk = sfft.rfftn(white, workers=workers)
     del white
     f0 = np.fft.fftfreq(n) * n
     fx = np.fft.rfftfreq(n) * n
@@ -105,7 +112,7 @@ def grf_peak_sources(rng: np.random.Generator, n: int, frac: float = 0.01):
     wk /= np.sqrt(kk)
     wk[0, 0, 0] = 0.0
     del kk
-    delta = sfft.irfftn(wk, s=(n, n, n), workers=-1).ravel()
+    delta = sfft.irfftn(wk, s=(n, n, n), workers=workers).ravel()
     del wk
     keep = int(math.floor(frac * n ** 3))
     part = np.argpartition(delta, delta.size - keep - 1)
@@ -166,19 +173,32 @@ def points_256c_40s(seed_base: int = 3, n: int = 256, K: int = 40) -> Workload:
     return Workload(f"grid{n}_slices{K}", [b])
 
 
+def _grf_slice(seed_base: int, k: int, n: int):
+    """GRF peak sources of slice k (one process of a pool)."""
+    return grf_peak_sources(np.random.default_rng([seed_base, 0, k]), n, workers=1)
+
+
 def bands_512c_60s(seed_base: int = 4, n: int = 512, K: int = 60,
-         horizons=(100.0, 80.0, 60.0, 40.0), recipe: str = "grf") -> Workload:
+         horizons=(100.0, 80.0, 60.0, 40.0), recipe: str = "grf", procs: int = 1) -> Workload:
     """512^3, 400 Mpc, 60 slices over 0-100 Mpc, 4 LW-like bands with
-    horizons 100/80/60/40 Mpc sharing the sources."""
+    horizons 100/80/60/40 Mpc sharing the sources. With procs > 1 the GRF
+    slices are drawn by a pool of that many processes (same values: each
+    slice has its own seed)."""
     L = 400.0 * n / 512
     r_max = 100.0 * n / 512
-    srcs = []
-    for k in range(K):
-        rng = np.random.default_rng([seed_base, 0, k])
-        if recipe == "grf":
-            srcs.append(grf_peak_sources(rng, n))
-        else:
-            srcs.append(uniform_sources(rng, n ** 3, int(0.01 * n ** 3)))
+    if recipe == "grf" and procs > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+            srcs = list(ex.map(_grf_slice, [seed_base] * K, range(K), [n] * K))
+    else:
+        srcs = []
+        for k in range(K):
+            rng = np.random.default_rng([seed_base, 0, k])
+            if recipe == "grf":
+                srcs.append(grf_peak_sources(rng, n))
+            else:
+                srcs.append(uniform_sources(rng, n ** 3, int(0.01 * n ** 3)))
     bands = [lw_band(h * n / 512) for h in horizons]
     b = Box(n=n, box=L, radii=equal_radii(r_max, K), supersample=4,
             bands=bands, sources=srcs)
@@ -230,3 +250,14 @@ def dense_grid(n: int, cells: np.ndarray, lum: np.ndarray, dtype=np.float64) -> 
     g = np.bincount(np.asarray(cells, np.int64), weights=np.asarray(lum, np.float64),
                     minlength=n ** 3)
     return g.astype(dtype, copy=False)
+
+
+def sources_digest(box: Box) -> str:
+    """SHA-256 of a box's per-slice point lists (cells then luminosities):
+    names the exact inputs a stored reference was computed from."""
+    import hashlib
+    h = hashlib.sha256()
+    for c, v in box.sources:
+        h.update(np.ascontiguousarray(c, np.int64).tobytes())
+        h.update(np.ascontiguousarray(v, np.float64).tobytes())
+    return h.hexdigest()

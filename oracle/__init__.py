@@ -14,6 +14,9 @@ Routes (Sec. 2.2, Eqs. 11-13 and algorithm steps 2-6):
                      Eq. 13 summed over slices, naive inverse, / N^3.
   * field_fft      - route F with a library FFT (scipy.fft, FP64) as the
                      transform step, for grids too large for the naive DFT.
+  * field_direct_support - route D summed over the kernel's support (the
+                     displacements that can meet each shell), for large grids
+                     with an outer radius well inside half the box.
   * field_per_slice_inverse - the paper's literal order (inverse per slice,
                      then sum; steps 5-6), used to check the spectral sum.
 """
@@ -59,6 +62,8 @@ def lib():
         L.or_field_direct.argtypes = [C.c_int, C.c_int, dp, ip, ip, dp, C.c_int64, ip, dp]
         L.or_field_direct_ondemand.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int,
                                                ap, ip, ip, dp, C.c_int64, ip, dp]
+        L.or_field_direct_support.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, C.c_int,
+                                              ap, ip, ip, dp, C.c_int64, ip, dp]
         L.or_dft3_naive.argtypes = [C.c_int, C.c_int, C.c_void_p]
         L.or_dft3_brute.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
         L.or_conv3_brute.argtypes = [C.c_int, dp, dp, dp]
@@ -184,6 +189,28 @@ def field_direct_ondemand(n: int, L: float, radii, m: int, at, sources,
                                         _iptr(cells), _dptr(lum), len(targets),
                                         _iptr(targets), _dptr(J))
     assert rc == 0
+    return J
+
+
+def field_direct_support(n: int, L: float, radii, m: int, bands, sources,
+                         targets: np.ndarray) -> np.ndarray:
+    """Route D written over the kernel's support: for each slice, the kernel
+    values at every displacement that can meet the slice's shell (from the
+    definition), times the slice's deposited sources. All bands at once;
+    returns [band, target]. Needs an outer radius below half the box minus
+    two cell diagonals (one periodic image)."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    K = len(radii) - 1
+    off, cells, lum = _flatten_sources(sources)
+    targets = np.ascontiguousarray(targets, dtype=np.int64)
+    nb = len(bands)
+    arr = (_Atten * nb)(*[_atten(b) for b in bands])
+    J = np.zeros((nb, len(targets)))
+    rc = lib().or_field_direct_support(n, L, K, _dptr(radii), m, nb, arr, _iptr(off), _iptr(cells),
+                                       _dptr(lum), len(targets), _iptr(targets), _dptr(J))
+    if rc == -2:
+        raise ValueError("outer radius too large for the single-image support route")
+    assert rc == 0, rc
     return J
 
 

@@ -399,6 +399,84 @@ int or_field_direct_ondemand(int N, double L, int K, const double *radii, int m,
     return 0;
 }
 
+/* Kernel-support version for large grids whose outer radius stays well inside
+ * half the box (one periodic image can reach a target): the same sum written
+ * over displacements, J_b(x) = sum_k sum_d G_{k,b}(d) S_k((x - d) mod N), where
+ * d runs over the cells whose minimum-image distance from the origin lies in
+ * [r_k - diag, r_{k+1} + diag] (G_{k,b} vanishes elsewhere: every subpoint of
+ * any other cell is farther than half a diagonal from the shell). S_k is
+ * the nearest-grid-point deposit of slice k's point list. All nb bands share
+ * the sources; J is nb x n_targets, band-major. Returns -2 when the outer
+ * radius is too large for a single image. */
+int or_field_direct_support(int N, double L, int K, const double *radii, int m, int nb,
+                            const or_atten *at,
+                            const int64_t *off, const int64_t *src_cell, const double *src_lum,
+                            int64_t n_targets, const int64_t *targets, double *J)
+{
+    if (nb < 1 || nb > 16) return -1;
+    kern_t kp[16];
+    for (int b = 0; b < nb; ++b)
+        if (kern_init(&kp[b], N, L, K, radii, m, &at[b])) return -1;
+    const double l = L / N, diag = sqrt(3.0) * l;
+    if (!(radii[K] + 2.0 * diag < 0.5 * L)) return -2;
+    const int64_t n3 = (int64_t)N * N * N;
+    double *S = (double *)malloc(sizeof(double) * n3);
+    nsum *acc = (nsum *)calloc((size_t)nb * n_targets, sizeof(nsum));
+    if (!S || !acc) { free(S); free(acc); return -3; }
+    for (int k = 0; k < K; ++k) {
+        if (off[k + 1] == off[k]) continue;
+        /* deposit of slice k */
+        memset(S, 0, sizeof(double) * n3);
+        for (int64_t s = off[k]; s < off[k + 1]; ++s) S[src_cell[s]] += src_lum[s];
+        /* displacements that can meet shell k */
+        const double lo = radii[k] - diag, hi = radii[k + 1] + diag;
+        const int R = (int)ceil(hi / l);
+        const int W = 2 * R + 1;
+        int64_t cand = (int64_t)W * W * W, nd = 0;
+        int32_t *dl = (int32_t *)malloc(sizeof(int32_t) * 3 * cand);
+        for (int64_t c = 0; c < cand; ++c) {
+            int d0 = (int)(c / ((int64_t)W * W)) - R, d1 = (int)((c / W) % W) - R, d2 = (int)(c % W) - R;
+            double r = sqrt((double)d0 * d0 + (double)d1 * d1 + (double)d2 * d2) * l;
+            if (r < lo || r > hi) continue;
+            dl[3 * nd] = d0; dl[3 * nd + 1] = d1; dl[3 * nd + 2] = d2;
+            ++nd;
+        }
+        /* kernel values there, from the definition */
+        double *g = (double *)malloc(sizeof(double) * nb * (nd > 0 ? nd : 1));
+        #pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < nd; ++i)
+            for (int b = 0; b < nb; ++b) {
+                double v = 0.0;
+                kern_accumulate(&kp[b], dl[3 * i], dl[3 * i + 1], dl[3 * i + 2], k, k + 1, &v);
+                g[(int64_t)b * nd + i] = v;
+            }
+        #pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t t = 0; t < n_targets; ++t) {
+            int64_t x = targets[t];
+            int xi = (int)(x / ((int64_t)N * N)), xj = (int)((x / N) % N), xk = (int)(x % N);
+            for (int b = 0; b < nb; ++b) {
+                nsum a = acc[(int64_t)b * n_targets + t];
+                const double *gb = g + (int64_t)b * nd;
+                for (int64_t i = 0; i < nd; ++i) {
+                    if (gb[i] == 0.0) continue;
+                    int c0 = ((xi - dl[3 * i]) % N + N) % N;
+                    int c1 = ((xj - dl[3 * i + 1]) % N + N) % N;
+                    int c2 = ((xk - dl[3 * i + 2]) % N + N) % N;
+                    double sv = S[((int64_t)c0 * N + c1) * N + c2];
+                    if (sv != 0.0) nadd(&a, gb[i] * sv);
+                }
+                acc[(int64_t)b * n_targets + t] = a;
+            }
+        }
+        free(g);
+        free(dl);
+    }
+    for (int64_t i = 0; i < (int64_t)nb * n_targets; ++i) J[i] = acc[i].s + acc[i].c;
+    free(S);
+    free(acc);
+    return 0;
+}
+
 /* ---- naive DFT (Eq. 12 convention) ------------------------------------- */
 
 /* Twiddle table e^{sign 2 pi i j / N}, j in [0, N), from long double libm. */

@@ -121,6 +121,56 @@ def test_node_rule_single_source_is_delayed_shell():
     np.testing.assert_allclose(G[0], expect0, rtol=1e-14, atol=0)
 
 
+def test_shell_ties_go_to_the_outer_shell():
+    """Reading of the closed window (Sec. 2.1): a node exactly at distance
+    r_k belongs to shell k only (half-open [r_k, r_{k+1})), and a node
+    exactly at r_K to no shell. With l = 1 and the node rule, node (3, 4, 0)
+    is exactly 5 from the source and (0, 0, 7) exactly 7; the expected shell
+    of every node comes from exact integer comparisons d^2 vs r_k^2."""
+    n, L = 16, 16.0
+    radii = np.array([0.0, 2.3, 5.0, 7.0])        # r_2 = 5 and r_3 = 7 are met exactly
+    G = oracle.build_G(n, L, radii, 1, li.Atten(kind=0))
+    idx = np.arange(n)
+    e = np.minimum(idx, n - idx)
+    d2 = e[:, None, None] ** 2 + e[None, :, None] ** 2 + e[None, None, :] ** 2   # exact integers
+    r2 = [0, None, 25, 49]                        # squares of the exact radii (r_1 = 2.3 is met by no node)
+    shell = np.full(d2.shape, -1)
+    shell[(d2 > 0) & (d2 * 100 < 529)] = 0        # d < 2.3  <=>  100 d^2 < 529
+    shell[(d2 * 100 >= 529) & (d2 < r2[2])] = 1
+    shell[(d2 >= r2[2]) & (d2 < r2[3])] = 2
+    ties = [(3, 4, 0), (0, 0, 5), (0, 3, 4), (0, 0, 7), (2, 3, 6), (6, 3, 2)]
+    assert shell[3, 4, 0] == 2 and shell[0, 0, 5] == 2 and shell[0, 0, 7] == -1 and shell[2, 3, 6] == -1
+    for k in (1, 2):
+        want = np.where(shell == k, 1.0 / (4 * np.pi * np.where(d2 > 0, d2, 1)), 0.0)
+        np.testing.assert_allclose(G[k], want, rtol=1e-15, atol=0)
+    for t in ties:
+        assert G[1][t] == 0.0                     # never in the inner shell as well
+    # the same through route D: a unit source in slice 2 is seen at the tie node
+    src = [(np.zeros(0, np.int64), np.zeros(0))] * 3
+    src = [src[0], src[1], (np.array([0], np.int64), np.array([1.0]))]
+    J = oracle.field_direct(G, src, np.array([(3 * n + 4) * n + 0, (0 * n + 0) * n + 7]))
+    assert abs(J[0] - 1.0 / (4 * np.pi * 25.0)) <= 1e-16 and J[1] == 0.0
+
+
+def test_support_route_equals_dense_route():
+    """Route D over the kernel's support (displacements near each shell,
+    all bands at once) against route D with the dense kernel, with ties,
+    attenuation, the paper's hard cut and an empty slice."""
+    n, L = 32, 40.0
+    radii = np.array([0.0, 2.5, 5.0, 7.5, 10.0, 12.5, 15.0])   # exact multiples of l = 1.25
+    bands = [li.Atten(kind=0), li.lw_band(12.0),
+             li.Atten(kind=2, a=1.7, s=116.29 * 0.1, p=0.68, c=0.7, cut=97.39 * 0.1)]
+    srcs = [li.random_sources([9, k], n, 40) for k in range(6)]
+    srcs[2] = (np.zeros(0, np.int64), np.zeros(0))
+    tg = li.sample_cells(5, n, 300)
+    JS = oracle.field_direct_support(n, L, radii, 2, bands, srcs, tg)
+    for b, at in enumerate(bands):
+        JD = oracle.field_direct(oracle.build_G(n, L, radii, 2, at), srcs, tg)
+        assert np.max(np.abs(JS[b] - JD)) <= 1e-14 * np.max(np.abs(JD))
+    with pytest.raises(ValueError):
+        oracle.field_direct_support(n, L, np.array([0.0, 10.0, 19.0]), 2, bands[:1], srcs[:2], tg)
+
+
 def test_causality_support_exact_zero():
     """A point source in slice k gives exactly 0 at nodes with no image
     distance inside [r_k, r_{k+1}) (route D, node rule)."""
