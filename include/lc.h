@@ -60,7 +60,9 @@ typedef enum {
     LC_EDEVICE = -3,       /* no usable gfx950 device, or a HIP call failed */
     LC_ESTATE = -4,        /* call out of order (e.g. field before kernels built) */
     LC_EUNSUPPORTED = -5,  /* valid but unsupported size or combination */
-    LC_ENONFINITE = -6     /* non-finite value found in a source grid */
+    LC_ENONFINITE = -6     /* a slice's sources hold a NaN or an infinity (their FP64
+                              sum is not finite); reported by lc_field with host
+                              outputs and by lc_check_sources */
 } lc_status;
 
 /* Arithmetic of the transforms and the slice sum. */
@@ -84,7 +86,7 @@ typedef enum { LC_MEM_HOST = 0, LC_MEM_DEVICE = 1 } lc_mem;
 
 /* One periodic box. */
 typedef struct {
-    int32_t n;            /* grid side N: 8..1024, N = 2^a 3^b, N even    */
+    int32_t n;            /* grid side N: 8..512, N = 2^a 3^b, N even     */
     int32_t n_slices;     /* K >= 1 lookback slices (algorithm step 1)    */
     int32_t n_bands;      /* B >= 1 radial factors sharing the sources    */
     int32_t supersample;  /* m: 1 (node rule) .. 8 subpoints per axis     */
@@ -145,13 +147,20 @@ typedef struct {
 typedef struct lc_plan_s lc_plan_t;
 
 /* Bytes of device workspace the plan needs (0 on an invalid descriptor;
- * the workspace fields of desc are ignored). Host only, no device call. */
+ * the workspace fields of desc are ignored). Host only, no device call.
+ * The storage follows the algorithm of Sec. 2.2: the transformed sources of
+ * every lookback slice (step 4, kept for the slice sum of step 6), the
+ * kernel spectra G^_{k,b} of every (slice, band) (step 3, precomputed once
+ * and stored, as the paragraph after the algorithm proposes), one
+ * accumulator spectrum per band, and builder scratch for step 2. */
 size_t lc_workspace_bytes(const lc_plan_desc *desc);
 
-/* Validate desc, carve the workspace, compute the FP64 host constants
- * (thresholds T_k, twiddle tables, self-cell averages) and upload them.
+/* Algorithm step 1: fix the box, the grid and the lookback slices of each
+ * box (radii r_k of the shells [r_k, r_{k+1}), Eq. 9 and the shell of step
+ * 2). Validates desc, carves the workspace, computes the FP64 host constants
+ * (thresholds T_k, twiddle tables, self-cell averages) and uploads them.
  * Errors: LC_EINVAL (bad field), LC_EUNSUPPORTED (N not 2^a 3^b in
- * 8..1024, m > 8, or r_0 = 0 with r_1 < (sqrt(3)/2) l so that the self
+ * 8..512, m > 8, or r_0 = 0 with r_1 < (sqrt(3)/2) l so that the self
  * cell would straddle two slices), LC_ENOMEM (workspace too small or
  * misaligned to 256 bytes), LC_EDEVICE (no gfx950 device). A plan of
  * several boxes also creates up to three side streams (default priority) on
@@ -173,6 +182,20 @@ int lc_build_greens(lc_plan_t *plan, int32_t box, int32_t band, const lc_atten *
  * pushed are zero. */
 int lc_push_sources(lc_plan_t *plan, int32_t box, int32_t slice, const lc_sources *src);
 
+/* Move the observing time forward by one slice (the paragraph after the
+ * algorithm of Sec. 2.2: the field is wanted at a sequence of observing
+ * times, and with slices of equal width aligned to the steps, the slice
+ * that was lookback k becomes lookback k+1). The plan's slice spectra form
+ * a ring: the oldest (lookback K-1) is dropped, every other slice moves one
+ * lookback slot older without being transformed again, and `src` becomes
+ * lookback slice 0 (step 4 for the new slice only). The kernels G^_{k,b}
+ * stay attached to the lookback index; rebuild them with lc_build_greens
+ * where they depend on the observing time (Eq. 17). A following lc_field
+ * then costs one forward transform, the slice sum over all K slices and one
+ * inverse per band. Errors as lc_push_sources; on error the ring is
+ * unchanged. */
+int lc_advance(lc_plan_t *plan, int32_t box, const lc_sources *src);
+
 /* Evaluate the field - algorithm steps 5-6 with the slice sum taken in
  * spectral space (linearity; one inverse per band instead of one per
  * slice). box = -1 selects all boxes, band = -1 all bands. out holds one
@@ -181,7 +204,8 @@ int lc_push_sources(lc_plan_t *plan, int32_t box, int32_t slice, const lc_source
 int lc_field(lc_plan_t *plan, int32_t box, int32_t band, void *const *out,
              int32_t dtype, int32_t mem);
 
-/* One whole step for every box: push all slices from srcs (box-major,
+/* One whole step for every box - algorithm steps 4-6 for every slice and
+ * band: push all slices from srcs (box-major, lookback order,
  * sum_b K_b entries, device memory only) and evaluate every band into out
  * (box-major, band, device memory). With use_graph = 1 the launch sequence
  * is captured in a HIP graph on first use and replayed while the argument
@@ -191,6 +215,16 @@ int lc_field(lc_plan_t *plan, int32_t box, int32_t band, void *const *out,
  * call, the work is complete when the plan's stream reaches the end of the
  * call. Outputs of different boxes must not overlap. */
 int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t dtype);
+
+/* Non-finite source check (LC_ENONFINITE): every field evaluation reduces
+ * each slice's sources in FP64 (the sum also gives the FP64 mean of the
+ * FP32 form, S^_k(0) of Eq. 13) and flags a slice whose sum is NaN or
+ * infinite. Synchronises the plan's stream, then returns LC_ENONFINITE if
+ * any evaluation of box `box` (-1: all boxes) since the last check flagged
+ * a slice, with the smallest flagged lookback index in *first_bad (may be
+ * NULL; -1 when none), and clears the flags. lc_field with host outputs
+ * performs the same check after its copies. */
+int lc_check_sources(lc_plan_t *plan, int32_t box, int32_t *first_bad);
 
 /* Release the plan's host state and its side streams (no caller memory is
  * freed). NULL is a no-op. */

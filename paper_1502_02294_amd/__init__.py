@@ -6,8 +6,10 @@ memory (the workspace and the buffers) and the HIP stream. There is no CPU
 path: if the library is missing, loading fails with an error.
 
 The C entry points are exposed under their own names (lc_plan,
-lc_build_greens, lc_push_sources, lc_field, lc_step, lc_destroy,
-lc_last_error, lc_workspace_bytes); `Plan` wraps them for torch tensors.
+lc_build_greens, lc_push_sources, lc_advance, lc_field, lc_step,
+lc_check_sources, lc_destroy, lc_last_error, lc_workspace_bytes); `Plan`
+wraps them for torch tensors and checks every tensor (device, dtype, size,
+layout) before its address is handed to the library.
 """
 from __future__ import annotations
 
@@ -26,9 +28,10 @@ LC_MEM_HOST, LC_MEM_DEVICE = 0, 1
 STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", -4: "LC_ESTATE",
                 -5: "LC_EUNSUPPORTED", -6: "LC_ENONFINITE"}
 
-EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_field",
-            "lc_step", "lc_destroy", "lc_last_error", "lc_greens_imag_ratio", "lc_greens_dc",
-            "lc_time_kernel", "lc_get_schedule", "lc_set_schedule"]
+EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance",
+            "lc_field", "lc_step", "lc_check_sources", "lc_destroy", "lc_last_error",
+            "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
+            "lc_set_schedule"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
  LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD, LC_KERNEL_YX_INV) = range(10)
@@ -88,6 +91,8 @@ def load():
     L.lc_plan.argtypes = [C.POINTER(lc_plan_desc), C.POINTER(C.c_void_p)]
     L.lc_build_greens.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_atten)]
     L.lc_push_sources.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_sources)]
+    L.lc_advance.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_sources)]
+    L.lc_check_sources.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
     L.lc_field.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_int32]
     L.lc_step.argtypes = [C.c_void_p, C.POINTER(lc_sources), C.POINTER(C.c_void_p), C.c_int32]
     L.lc_destroy.argtypes = [C.c_void_p]
@@ -98,9 +103,9 @@ def load():
     L.lc_time_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.lc_get_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
     L.lc_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
-    for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_field", "lc_step",
-                 "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
-                 "lc_set_schedule"]:
+    for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance", "lc_field", "lc_step",
+                 "lc_check_sources", "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel",
+                 "lc_get_schedule", "lc_set_schedule"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -161,6 +166,18 @@ def lc_push_sources(plan, box: int, slice_: int, src: lc_sources):
     _check(load().lc_push_sources(plan, box, slice_, C.byref(src)))
 
 
+def lc_advance(plan, box: int, src: lc_sources):
+    _check(load().lc_advance(plan, box, C.byref(src)))
+
+
+def lc_check_sources(plan, box: int = -1) -> int:
+    """-1 when no evaluation since the last check saw a non-finite source,
+    else raises LCError(LC_ENONFINITE) naming the first flagged lookback slice."""
+    v = C.c_int32(-1)
+    _check(load().lc_check_sources(plan, box, C.byref(v)))
+    return int(v.value)
+
+
 def lc_field(plan, box: int, band: int, outs: Sequence[int], dtype: int, mem: int):
     arr = (C.c_void_p * len(outs))(*[C.c_void_p(o) for o in outs])
     _check(load().lc_field(plan, box, band, arr, dtype, mem))
@@ -174,6 +191,45 @@ def lc_step(plan, srcs: Sequence[lc_sources], outs: Sequence[int], dtype: int):
 
 def lc_destroy(plan):
     load().lc_destroy(plan)
+
+
+# ---- tensor checks ----------------------------------------------------------------------
+
+def _same_device(t, device) -> bool:
+    if t.device.type != device.type:
+        return False
+    return device.index is None or t.device.index == device.index
+
+
+def check_tensor(t, what: str, *, dtypes, numel=None, device=None, allow_host: bool = False,
+                 copy_ok: bool = True):
+    """Check a tensor before its address goes to the library; returns the
+    tensor to pass (a contiguous copy when `copy_ok` and `t` is not
+    contiguous; the caller keeps it alive until the stream has used it).
+
+    dtypes: allowed torch dtypes; numel: required element count; device:
+    the plan's device (CPU tensors pass only with allow_host). Raises
+    TypeError for a wrong type or dtype, ValueError for a wrong size,
+    device or layout."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor, not {type(t).__name__}")
+    if t.dtype not in dtypes:
+        names = ", ".join(str(d).replace("torch.", "") for d in dtypes)
+        raise TypeError(f"{what} has dtype {str(t.dtype).replace('torch.', '')}; expected one of {names}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements; expected {numel}")
+    if device is not None:
+        if t.device.type == "cpu":
+            if not allow_host and device.type != "cpu":
+                raise ValueError(f"{what} is in host memory; expected a tensor on {device}")
+        elif not _same_device(t, device):
+            raise ValueError(f"{what} is on {t.device}; expected {device}")
+    if not t.is_contiguous():
+        if not copy_ok:
+            raise ValueError(f"{what} must be contiguous (it is written in place)")
+        t = t.contiguous()
+    return t
 
 
 # ---- torch-facing convenience ----------------------------------------------------------
@@ -194,6 +250,8 @@ class Plan:
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.precision = precision
         self.boxes = list(boxes)
         self._keep = []
@@ -234,55 +292,101 @@ class Plan:
         if cur != self.stream:
             cur.wait_stream(self.stream)
 
+    def _call(self, fn, *args):
+        """One library call ordered against torch's current stream (also when
+        the call fails: work it enqueued before failing stays ordered)."""
+        self._enter()
+        try:
+            return fn(*args)
+        finally:
+            self._leave()
+
     def build_greens(self, box: int = 0, band: int = 0, atten=None):
         at = atten if atten is not None else self.boxes[box].bands[band]
-        self._enter()
-        lc_build_greens(self.handle, box, band, make_atten(at))
-        self._leave()
+        self._call(lc_build_greens, self.handle, box, band, make_atten(at))
 
     def build_all(self):
         for bi, b in enumerate(self.boxes):
             for band in range(len(b.bands)):
                 self.build_greens(bi, band)
 
-    def push_grid(self, box: int, slice_: int, grid):
-        """Dense source grid: a torch tensor (device or CPU) of N^3 float32/float64."""
-        t = grid.contiguous()
-        dt = LC_F64 if t.dtype == self.torch.float64 else LC_F32
-        if t.dtype not in (self.torch.float32, self.torch.float64):
-            raise TypeError("source grid must be float32 or float64")
+    def _box_n(self, box: int) -> int:
+        if not 0 <= box < len(self.boxes):
+            raise ValueError(f"box {box} out of range [0, {len(self.boxes)})")
+        return self.boxes[box].n
+
+    def _grid_source(self, box: int, grid, allow_host: bool, what: str):
+        """lc_sources of a dense grid (and the tensor to keep alive)."""
+        torch = self.torch
+        n = self._box_n(box)
+        t = check_tensor(grid, what, dtypes=(torch.float32, torch.float64), numel=n ** 3,
+                         device=self.device, allow_host=allow_host)
+        dt = LC_F64 if t.dtype == torch.float64 else LC_F32
         mem = LC_MEM_DEVICE if t.is_cuda else LC_MEM_HOST
-        src = lc_sources(0, dt, mem, 0, t.data_ptr(), 0, None, None)
-        self._enter()
-        lc_push_sources(self.handle, box, slice_, src)
-        self._leave()
+        return lc_sources(0, dt, mem, 0, t.data_ptr(), 0, None, None), t
+
+    def _point_source(self, box: int, cells, lum, allow_host: bool, what: str):
+        """lc_sources of a point list (and the tensors to keep alive)."""
+        torch = self.torch
+        self._box_n(box)
+        c = check_tensor(cells, what + " cells", dtypes=(torch.int64,), device=self.device,
+                         allow_host=allow_host)
+        v = check_tensor(lum, what + " luminosities", dtypes=(torch.float32, torch.float64),
+                         numel=c.numel(), device=self.device, allow_host=allow_host)
+        if c.device != v.device:
+            raise ValueError(f"{what}: cells on {c.device} but luminosities on {v.device}")
+        dt = LC_F64 if v.dtype == torch.float64 else LC_F32
+        mem = LC_MEM_DEVICE if c.is_cuda else LC_MEM_HOST
+        src = lc_sources(1, dt, mem, 0, None, int(c.numel()), c.data_ptr() if c.numel() else None,
+                         v.data_ptr() if v.numel() else None)
+        return src, (c, v)
+
+    def _source(self, box: int, s, allow_host: bool, what: str):
+        if isinstance(s, (tuple, list)):
+            if len(s) != 2:
+                raise ValueError(f"{what}: a point list is a (cells, lum) pair")
+            return self._point_source(box, s[0], s[1], allow_host, what)
+        return self._grid_source(box, s, allow_host, what)
+
+    def push_grid(self, box: int, slice_: int, grid):
+        """Dense source grid: a torch tensor (on the plan's device or on the
+        host) of N^3 float32/float64 values."""
+        src, t = self._grid_source(box, grid, True, "source grid")
+        self._call(lc_push_sources, self.handle, box, slice_, src)
         return t  # caller keeps it alive until the stream reaches the call
 
     def push_points(self, box: int, slice_: int, cells, lum):
         """Point list: int64 cells and float32/float64 luminosities (torch
-        tensors on one device)."""
-        c = cells.contiguous()
-        v = lum.contiguous()
-        dt = LC_F64 if v.dtype == self.torch.float64 else LC_F32
-        mem = LC_MEM_DEVICE if c.is_cuda else LC_MEM_HOST
-        src = lc_sources(1, dt, mem, 0, None, int(c.numel()), c.data_ptr() if c.numel() else None,
-                         v.data_ptr() if v.numel() else None)
-        self._enter()
-        lc_push_sources(self.handle, box, slice_, src)
-        self._leave()
-        return c, v
+        tensors on one device, the plan's or the host)."""
+        src, keep = self._point_source(box, cells, lum, True, "point list")
+        self._call(lc_push_sources, self.handle, box, slice_, src)
+        return keep
+
+    def advance(self, box: int, sources):
+        """Next observing time (lc_advance): `sources` (a dense grid tensor
+        or a (cells, lum) pair, device or host) become lookback slice 0 and
+        every other slice moves one slot older. Returns the tensors to keep
+        alive until the stream has run the call."""
+        src, keep = self._source(box, sources, True, "advance sources")
+        self._call(lc_advance, self.handle, box, src)
+        return keep
+
+    def check_sources(self, box: int = -1) -> None:
+        """Raise LCError(LC_ENONFINITE) if an evaluation since the last check
+        met a NaN or infinite source (synchronises the plan's stream)."""
+        self._call(lc_check_sources, self.handle, box)
 
     def field(self, box: int = 0, band: int = 0, dtype=None, out=None):
         torch = self.torch
-        n = self.boxes[box].n
+        n = self._box_n(box)
         dtype = dtype or (torch.float64 if self.precision == LC_PREC_FP64 else torch.float32)
         if out is None:
             out = torch.empty((n, n, n), dtype=dtype, device=self.device)
+        out = check_tensor(out, "output field", dtypes=(torch.float32, torch.float64), numel=n ** 3,
+                           device=self.device, allow_host=True, copy_ok=False)
         dt = LC_F64 if out.dtype == torch.float64 else LC_F32
         mem = LC_MEM_DEVICE if out.is_cuda else LC_MEM_HOST
-        self._enter()
-        lc_field(self.handle, box, band, [out.data_ptr()], dt, mem)
-        self._leave()
+        self._call(lc_field, self.handle, box, band, [out.data_ptr()], dt, mem)
         return out
 
     def greens_dc(self, box: int = 0, band: int = 0):
@@ -299,9 +403,7 @@ class Plan:
     def time_kernel(self, kernel: int, box: int = 0, reps: int = 10) -> float:
         """Mean milliseconds per launch of one kernel of the path (HIP events)."""
         v = C.c_double()
-        self._enter()
-        _check(load().lc_time_kernel(self.handle, box, kernel, reps, C.byref(v)))
-        self._leave()
+        self._call(lambda: _check(load().lc_time_kernel(self.handle, box, kernel, reps, C.byref(v))))
         return float(v.value)
 
     def get_schedule(self, box: int = 0) -> dict:
@@ -315,39 +417,52 @@ class Plan:
         cur = self.get_schedule(box)
         cur.update(kw)
         s = lc_schedule(*[int(cur[f]) for f, _ in lc_schedule._fields_])
-        self._enter()
-        _check(load().lc_set_schedule(self.handle, box, C.byref(s)))
-        self._leave()
+        self._call(lambda: _check(load().lc_set_schedule(self.handle, box, C.byref(s))))
 
     def step(self, grids, outs, dtype=None):
         """One whole step (lc_step): push every slice of every box (box-major
         list of device sources: a dense grid tensor, or a point list given as
         a (cells, lum) pair of tensors) and evaluate every band into outs
-        (box-major, band; device tensors of one dtype). Returns the point-list
-        tensors passed on (contiguous copies where needed), which must stay
-        alive until the stream has run the step."""
+        (box-major, band; device tensors of one dtype). Returns, per source,
+        the tensor (or (cells, lum) pair) handed to the library, contiguous
+        copies where needed; they must stay alive until the stream has run
+        the step."""
         torch = self.torch
+        nsl = [len(b.radii) - 1 for b in self.boxes]
+        nbd = [len(b.bands) for b in self.boxes]
+        if len(grids) != sum(nsl):
+            raise ValueError(f"step takes {sum(nsl)} sources (all slices of all boxes), got {len(grids)}")
+        if len(outs) != sum(nbd):
+            raise ValueError(f"step takes {sum(nbd)} outputs (all bands of all boxes), got {len(outs)}")
         srcs, keep = [], []
-        for g in grids:
-            if isinstance(g, (tuple, list)):
-                c, v = g[0].contiguous(), g[1].contiguous()
-                dt = LC_F64 if v.dtype == torch.float64 else LC_F32
-                srcs.append(lc_sources(1, dt, LC_MEM_DEVICE, 0, None, int(c.numel()),
-                                       c.data_ptr() if c.numel() else None, v.data_ptr() if v.numel() else None))
-                keep.append((c, v))
-            else:
-                dt = LC_F64 if g.dtype == torch.float64 else LC_F32
-                srcs.append(lc_sources(0, dt, LC_MEM_DEVICE, 0, g.data_ptr(), 0, None, None))
+        i = 0
+        for bi, K in enumerate(nsl):
+            for k in range(K):
+                src, kp = self._source(bi, grids[i], False, f"box {bi} slice {k} sources")
+                srcs.append(src)
+                keep.append(kp)
+                i += 1
+        odts = {o.dtype for o in outs}
+        if len(odts) != 1:
+            raise TypeError("step outputs must share one dtype")
+        i = 0
+        for bi, B in enumerate(nbd):
+            for b in range(B):
+                check_tensor(outs[i], f"box {bi} band {b} output", dtypes=(torch.float32, torch.float64),
+                             numel=self.boxes[bi].n ** 3, device=self.device, copy_ok=False)
+                i += 1
         odt = LC_F64 if outs[0].dtype == torch.float64 else LC_F32
-        self._enter()
-        lc_step(self.handle, srcs, [o.data_ptr() for o in outs], odt)
-        self._leave()
+        self._call(lc_step, self.handle, srcs, [o.data_ptr() for o in outs], odt)
         return keep
 
     def close(self):
+        """Destroy the plan and drop its workspace (after the plan's stream
+        has finished with it)."""
         if getattr(self, "handle", None):
+            self.stream.synchronize()
             lc_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -239,7 +239,7 @@ template <int N> static int x_wgs_t() {
 }
 
 int x_pass_wgs(int n) {
-    if (x_rows_supported(n)) return x_rows_wgs(n);   // the FP32 x pass there (the only one with DC partials)
+    if (x_rows_supported(n)) return x_rows_wgs(n);   // the FP32 x pass there
     switch (n) {
 #define W_(N) case N: return x_wgs_t<N>();
         W_(8) W_(12) W_(16) W_(24) W_(32) W_(48) W_(64) W_(96) W_(128) W_(192) W_(256) W_(384) W_(512)

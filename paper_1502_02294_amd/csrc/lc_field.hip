@@ -96,6 +96,7 @@ struct FusedDev {
     double inv_n3;
     double *mu;
     int32_t K;
+    int32_t ring;              // lookback k lives in spectrum slot (k + ring) mod K
 };
 
 // Processing order of the main tiles in the rounds schedule. Main tile
@@ -173,7 +174,10 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
 #pragma unroll
         for (int b = 0; b < NB_; ++b) {
             double v = 0.0;
-            for (int k = threadIdx.x; k < a.K; k += 64) v += a.g0[(int64_t)k * a.B + a.band0 + b] * a.sk[k];
+            for (int k = threadIdx.x; k < a.K; k += 64) {
+                const int slot = k + a.ring < a.K ? k + a.ring : k + a.ring - a.K;
+                v += a.g0[(int64_t)k * a.B + a.band0 + b] * a.sk[slot];
+            }
             for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
             if (threadIdx.x == 0) a.mu[a.band0 + b] = v * a.inv_n3;
         }
@@ -255,7 +259,9 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // loads issued after it, so the prefetched slices stay in flight.
         const int kend = k0 + (k1 - k0 + PF - 1) / PF * PF;
         auto spec_at = [&](int k) {
-            return (const char *)(a.spec + (int64_t)(k < k1 ? k : k1 - 1) * a.spec_stride);
+            int slot = (k < k1 ? k : k1 - 1) + a.ring;
+            if (slot >= a.K) slot -= a.K;
+            return (const char *)(a.spec + (int64_t)slot * a.spec_stride);
         };
         // first-pass inputs of the next PF slices, kept in flight in a ring of
         // register buffers (PF slices of HBM latency hidden behind compute);
@@ -652,7 +658,7 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
     d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
     d.rounds = fa.rounds; d.tiles = tiles;
-    d.sk = fa.sk; d.g0 = fa.g0; d.inv_n3 = fa.inv_n3; d.mu = fa.mu; d.K = fa.K;
+    d.sk = fa.sk; d.g0 = fa.g0; d.inv_n3 = fa.inv_n3; d.mu = fa.mu; d.K = fa.K; d.ring = fa.ring;
     // the split table serves the stream-K mode's merge in the inverse y pass;
     // the rounds mode splits no tile and its inverse pass does not read it
     if (!fa.rounds)
@@ -788,7 +794,8 @@ int fused_cpw(int n) {
 // Stage 2: one workgroup forms mu_b from the slice sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void dc_slice_kernel(const double *__restrict__ dcpart, int W,
-                                                       double *__restrict__ sk) {
+                                                       double *__restrict__ sk, int *__restrict__ status,
+                                                       int ring, int K) {
     __shared__ double red[256];
     const int k = blockIdx.x;
     double s = 0.0;
@@ -799,12 +806,47 @@ __global__ __launch_bounds__(256) void dc_slice_kernel(const double *__restrict_
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sk[k] = red[0];
+    if (threadIdx.x == 0) {
+        sk[k] = red[0];
+        // a NaN or infinite source value makes its slice's FP64 sum non-finite
+        if (status && !isfinite(red[0])) {
+            atomicAdd(&status[0], 1);
+            atomicMin(&status[1], k >= ring ? k - ring : k - ring + K);
+        }
+    }
 }
 
-hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, hipStream_t st) {
-    if (K < 1 || W < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(dc_slice_kernel, dim3(K), dim3(256), 0, st, dcpart, W, sk);
+template <typename T>
+__global__ __launch_bounds__(64) void spec_dc_kernel(const cx<T> *__restrict__ spec, int64_t stride, int K,
+                                                     double *__restrict__ sk, int *__restrict__ status,
+                                                     int ring) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const double v = (double)spec[(int64_t)k * stride].x;
+    sk[k] = v;
+    if (!isfinite(v)) {
+        atomicAdd(&status[0], 1);
+        atomicMin(&status[1], k >= ring ? k - ring : k - ring + K);
+    }
+}
+
+hipError_t launch_spec_dc(const void *spec, bool f64, int64_t stride, int K, double *sk, int *status, int ring,
+                          hipStream_t st) {
+    if (K < 1 || ring < 0 || ring >= K) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((K + 63) / 64));
+    if (f64)
+        hipLaunchKernelGGL(spec_dc_kernel<double>, grid, dim3(64), 0, st, (const cx<double> *)spec, stride, K, sk,
+                           status, ring);
+    else
+        hipLaunchKernelGGL(spec_dc_kernel<float>, grid, dim3(64), 0, st, (const cx<float> *)spec, stride, K, sk,
+                           status, ring);
+    return hipGetLastError();
+}
+
+hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, int *status, int ring,
+                            hipStream_t st) {
+    if (K < 1 || W < 1 || ring < 0 || ring >= K) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dc_slice_kernel, dim3(K), dim3(256), 0, st, dcpart, W, sk, status, ring, K);
     return hipGetLastError();
 }
 

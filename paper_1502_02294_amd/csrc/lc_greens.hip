@@ -171,6 +171,19 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *__restrict__ p,
         p[e] = 0u;
 }
 
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *__restrict__ p, int64_t count, int32_t v) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(wgs), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);

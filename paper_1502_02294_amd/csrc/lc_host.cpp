@@ -215,16 +215,23 @@ bool is_2a3b(int n) {
 
 struct BoxPlan {
     int n = 0, K = 0, B = 0, m = 1, conserve = 0;
+    // ring of slice spectra: lookback slice k is stored in slot (head + k) mod K
+    // (lc_advance moves the head back by one, making the oldest slot the newest)
+    int head = 0;
+    int slot(int k) const { const int s = head + k; return s >= K ? s - K : s; }
     double L = 0, l = 0, h = 0;
     std::vector<double> radii, T;
     std::vector<int> built, kcount;
-    std::vector<uint8_t> pushed;
-    // dense device sources of the most recent push of each slice (diagnostic timing)
+    std::vector<uint8_t> pushed;          // per slot
+    // dense device sources of the most recent push of each slot (diagnostic timing)
     std::vector<const void *> last_src;
     std::vector<uint8_t> last_src_f64;
     // device regions
     char *spec = nullptr, *acc = nullptr, *ghat = nullptr;
     double *ghat0 = nullptr, *dcpart = nullptr, *mu = nullptr, *sk = nullptr;
+    // non-finite source sums seen by the DC reduction since the last query:
+    // {count, smallest lookback index} (device, {0, INT32_MAX} when clear)
+    int *status = nullptr;
     char *part = nullptr;        // FP32 form: second parts of split fused tiles, 2 bands
     int *split_tab = nullptr;    // per band pair slot: tile -> part slot
     int64_t max_parts = 0, part_stride = 0, tiles = 0;
@@ -276,8 +283,8 @@ namespace {
 struct Layout {
     size_t total = 0;
     struct BoxOff {
-        size_t spec, acc, ghat, ghat0, dcpart, mu, sk, part, split_tab, maxima, tw_half, tw_full, twist, tw64_half,
-            tw64_full, twist64;
+        size_t spec, acc, ghat, ghat0, dcpart, mu, sk, status, part, split_tab, maxima, tw_half, tw_full, twist,
+            tw64_half, tw64_full, twist64;
     };
     std::vector<BoxOff> box;
     size_t scratch_real = 0, scratch_spec = 0;
@@ -294,10 +301,8 @@ int validate(const lc_plan_desc *d) {
     for (int b = 0; b < d->n_boxes; ++b) {
         const lc_box_desc &x = d->boxes[b];
         if (x.reserved != 0) return fail(LC_EINVAL, "box %d: reserved field must be 0", b);
-        if (x.n < 8 || x.n > 1024 || (x.n % 2) || !is_2a3b(x.n))
-            return fail(LC_EUNSUPPORTED, "box %d: N=%d must be even, 2^a 3^b, in 8..1024", b, x.n);
-        if (!supported_n(x.n))
-            return fail(LC_EUNSUPPORTED, "box %d: N=%d is not compiled in (8..512)", b, x.n);
+        if (x.n < 8 || x.n > 512 || (x.n % 2) || !is_2a3b(x.n) || !supported_n(x.n))
+            return fail(LC_EUNSUPPORTED, "box %d: N=%d is not compiled in (even, 2^a 3^b, 8..512)", b, x.n);
         if (x.n_slices < 1 || x.n_slices > 1024)
             return fail(LC_EINVAL, "box %d: n_slices must be in [1, 1024]", b);
         if (x.n_bands < 1 || x.n_bands > 64) return fail(LC_EINVAL, "box %d: n_bands must be in [1, 64]", b);
@@ -344,6 +349,7 @@ Layout layout_of(const lc_plan_desc *d) {
         o.dcpart = take((size_t)K * std::max(x_pass_wgs(n), 2 * n) * 8);
         o.mu = take((size_t)B * 8);
         o.sk = take((size_t)K * 8);
+        o.status = take(2 * sizeof(int32_t));
         if (d->precision == LC_PREC_FP32) {
             o.part = take((size_t)2 * kMaxParts * n * fused_cpw(n) * 8);
             o.split_tab = take((size_t)((B + 1) / 2) * fused_tiles(n) * 4);
@@ -631,6 +637,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         bp.spec = p->ws + o.spec; bp.acc = p->ws + o.acc; bp.ghat = p->ws + o.ghat;
         bp.ghat0 = (double *)(p->ws + o.ghat0); bp.dcpart = (double *)(p->ws + o.dcpart);
         bp.mu = (double *)(p->ws + o.mu); bp.sk = (double *)(p->ws + o.sk);
+        bp.status = (int *)(p->ws + o.status);
         if (p->prec == LC_PREC_FP32) {
             bp.part = p->ws + o.part;
             bp.split_tab = (int *)(p->ws + o.split_tab);
@@ -678,6 +685,8 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         HIPCHK(launch_fill_bytes(bp.spec, (int64_t)bp.K * spec_elems(n) * cs, p->stream));
         HIPCHK(launch_fill_f64(bp.dcpart, (int64_t)bp.K * bp.dc_cap(), 0.0, p->stream));
         HIPCHK(launch_fill_f64(bp.ghat0, (int64_t)bp.K * bp.B, 0.0, p->stream));
+        HIPCHK(launch_fill_i32(bp.status, 1, 0, p->stream));
+        HIPCHK(launch_fill_i32(bp.status + 1, 1, INT32_MAX, p->stream));
         p->boxes.push_back(std::move(bp));
     }
     if (d->autotune && p->prec == LC_PREC_FP32) {
@@ -784,9 +793,13 @@ int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at)
     }
     bp.kcount[band] = kc;
     bp.built[band] = 1;
+    // a captured step holds this band's slice count (launch shapes of the
+    // slice sum): the next lc_step captures again
+    p->gkey.clear();
     return ok();
 }
 
+// Stage lookback slice `slice` of a box (its ring slot) on the plan's stream.
 static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
     BoxPlan &bp = p->boxes[box];
     const int n = bp.n;
@@ -794,12 +807,13 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
     hipStream_t st = p->stream;
     const void *in = nullptr;
     bool in_f64 = s->dtype == LC_F64;
-    bp.last_src[slice] = nullptr;
+    const int slot = bp.slot(slice);
+    bp.last_src[slot] = nullptr;
     if (s->kind == 0) {
         if (s->mem == LC_MEM_DEVICE) {
             in = s->grid;
-            bp.last_src[slice] = s->grid;
-            bp.last_src_f64[slice] = in_f64 ? 1 : 0;
+            bp.last_src[slot] = s->grid;
+            bp.last_src_f64[slot] = in_f64 ? 1 : 0;
         } else {
             HIPCHK(hipMemcpyAsync(p->scratch_real, s->grid, (size_t)n3 * (in_f64 ? 8 : 4),
                                   hipMemcpyHostToDevice, st));
@@ -822,8 +836,9 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
         in = p->scratch_real;
     }
     const size_t cs = p->t_f64 ? 16 : 8;
-    char *spec = bp.spec + (size_t)slice * spec_elems(n) * cs;
-    double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slice * bp.dcw : nullptr;
+    char *spec = bp.spec + (size_t)slot * spec_elems(n) * cs;
+    // FP64 input sums (the FP32 form's FP64 mean and its non-finite check)
+    double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slot * bp.dcw : nullptr;
     if (bp.use_xy) {
         SrcTab tab;
         tab.p[0] = in;
@@ -834,7 +849,7 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
         HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
     }
     if (p->prec != LC_PREC_FP32) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
-    bp.pushed[slice] = 1;
+    bp.pushed[slot] = 1;
     return LC_OK;
 }
 
@@ -849,6 +864,24 @@ int lc_push_sources(lc_plan_t *p, int32_t box, int32_t slice, const lc_sources *
     return rc ? rc : ok();
 }
 
+int lc_advance(lc_plan_t *p, int32_t box, const lc_sources *s) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    int rc = valid_sources(bp, s);
+    if (rc) return rc;
+    // the oldest slot becomes lookback slice 0; every other slice moves one
+    // lookback slot older
+    const int prev = bp.head;
+    bp.head = bp.head == 0 ? bp.K - 1 : bp.head - 1;
+    rc = push_impl(p, box, 0, s);
+    if (rc) {
+        bp.head = prev;
+        return rc;
+    }
+    return ok();
+}
+
 // Field of one box for bands [b0, b1) into device pointers outp[b - b0].
 static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64, hipStream_t st) {
     BoxPlan &bp = p->boxes[box];
@@ -856,9 +889,14 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
     const size_t cs = p->t_f64 ? 16 : 8;
     const int64_t se = spec_elems(n);
     const double inv_n3 = 1.0 / ((double)n * n * n);
+    // per-slice source sums (per ring slot), with the non-finite check: the
+    // FP32 form reduces its FP64 input sums, from which the fused z pass
+    // forms the FP64 band means; the plain forms read each spectrum's DC bin
+    if (p->prec == LC_PREC_FP32)
+        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.sk, bp.status, bp.head, st));
+    else
+        HIPCHK(launch_spec_dc(bp.spec, p->t_f64, se, K, bp.sk, bp.status, bp.head, st));
     if (p->prec == LC_PREC_FP32) {
-        // per-slice input sums; the fused z pass reduces the band means
-        HIPCHK(launch_dc_reduce(bp.dcpart, K, bp.dcw, bp.sk, st));
         for (int b = b0; b < b1;) {
             const int nb = std::min(2, b1 - b);
             int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;
@@ -873,6 +911,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.split_tab = tab;
             fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             fa.parity = bp.parity() ? 1 : 0;
+            fa.ring = bp.head;
             fa.sk = bp.sk; fa.g0 = bp.ghat0; fa.inv_n3 = inv_n3; fa.mu = bp.mu;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
@@ -897,7 +936,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             const int kc = bp.kcount[b];
             if (kc == 0) HIPCHK(launch_fill_bytes(acc, se * cs, st));
             for (int k = 0; k < kc; ++k)
-                HIPCHK(launch_mac_plain(n, p->t_f64, acc, bp.spec + (size_t)k * se * cs,
+                HIPCHK(launch_mac_plain(n, p->t_f64, acc, bp.spec + (size_t)bp.slot(k) * se * cs,
                                         bp.ghat + ((size_t)k * bp.B + b) * oct_elems(n) * rs, k == 0, st));
             HIPCHK(launch_col(n, p->t_f64, 2, false, acc, bp.tw_full, st));
             HIPCHK(launch_col(n, p->t_f64, 1, false, acc, bp.tw_full, st));
@@ -906,6 +945,29 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
         }
     }
     return LC_OK;
+}
+
+// Read and clear the non-finite source status of boxes [x0, x1) (the stream
+// must have reached the reductions): LC_ENONFINITE naming the first box with
+// a flagged slice, else LC_OK.
+static int take_status(lc_plan_t *p, int x0, int x1, int32_t *first_bad) {
+    int code = LC_OK;
+    for (int x = x0; x < x1; ++x) {
+        BoxPlan &bp = p->boxes[x];
+        int32_t st[2];
+        HIPCHK(hipMemcpyAsync(st, bp.status, sizeof(st), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (st[0] == 0) continue;
+        HIPCHK(launch_fill_i32(bp.status, 1, 0, p->stream));
+        HIPCHK(launch_fill_i32(bp.status + 1, 1, INT32_MAX, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (code == LC_OK) {
+            if (first_bad) *first_bad = st[1];
+            code = fail(LC_ENONFINITE, "box %d: %d slice evaluation(s) with non-finite sources, first at lookback slice %d",
+                        x, st[0], st[1]);
+        }
+    }
+    return code;
 }
 
 int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t dtype, int32_t mem) {
@@ -947,7 +1009,22 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
         }
         o += (size_t)(b1 - b0);
     }
+    if (mem == LC_MEM_HOST) {
+        // the stream is synchronised: report non-finite sources now
+        int rc = take_status(p, x0, x1, nullptr);
+        if (rc) return rc;
+    }
     return ok();
+}
+
+int lc_check_sources(lc_plan_t *p, int32_t box, int32_t *first_bad) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    const int nbx = (int)p->boxes.size();
+    if (box < -1 || box >= nbx) return fail(LC_EINVAL, "box %d out of range", box);
+    if (first_bad) *first_bad = -1;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const int rc = take_status(p, box < 0 ? 0 : box, box < 0 ? nbx : box + 1, first_bad);
+    return rc ? rc : ok();
 }
 
 // One box of lc_step on stream st: its slices' forward passes (groups of up
@@ -968,16 +1045,19 @@ static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *ou
             ++k;
             continue;
         }
+        // a batch takes consecutive lookback slices in consecutive ring slots
+        const int slot0 = bp.slot(k);
         int cnt = 0;
         SrcTab tab;
-        while (k + cnt < bp.K && cnt < bp.push_group && srcs[k + cnt].kind == 0 && srcs[k + cnt].dtype == s0.dtype) {
+        while (k + cnt < bp.K && cnt < bp.push_group && srcs[k + cnt].kind == 0 && srcs[k + cnt].dtype == s0.dtype &&
+               slot0 + cnt < bp.K) {
             tab.p[cnt] = srcs[k + cnt].grid;
-            bp.last_src[k + cnt] = srcs[k + cnt].grid;
-            bp.last_src_f64[k + cnt] = s0.dtype == LC_F64 ? 1 : 0;
+            bp.last_src[slot0 + cnt] = srcs[k + cnt].grid;
+            bp.last_src_f64[slot0 + cnt] = s0.dtype == LC_F64 ? 1 : 0;
             ++cnt;
         }
-        char *spec = bp.spec + (size_t)k * se * cs;
-        double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)k * bp.dcw : nullptr;
+        char *spec = bp.spec + (size_t)slot0 * se * cs;
+        double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slot0 * bp.dcw : nullptr;
         if (bp.use_xy) {
             HIPCHK(launch_xy_fwd_batch(n, tab, cnt, s0.dtype == LC_F64, spec, se, bp.tw_half, bp.twist, bp.tw_full,
                                        dcp, bp.dcw, bp.xy_variant, st));
@@ -987,7 +1067,7 @@ static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *ou
             HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, st));
         }
         if (p->prec != LC_PREC_FP32) HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
-        for (int j = 0; j < cnt; ++j) bp.pushed[k + j] = 1;
+        for (int j = 0; j < cnt; ++j) bp.pushed[slot0 + j] = 1;
         k += cnt;
     }
     return field_box(p, x, 0, bp.B, out, dtype == LC_F64, st);
@@ -1072,6 +1152,7 @@ int lc_step(lc_plan_t *p, const lc_sources *srcs, void *const *out, int32_t dtyp
     std::memcpy(key.data(), &dtype, sizeof(int32_t));
     key.insert(key.end(), (const uint8_t *)srcs, (const uint8_t *)(srcs + ns));
     key.insert(key.end(), (const uint8_t *)out, (const uint8_t *)(out + no));
+    for (auto &bp : p->boxes) key.insert(key.end(), (const uint8_t *)&bp.head, (const uint8_t *)(&bp.head + 1));
     if (!p->gexec || key != p->gkey) {
         if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
         if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
@@ -1182,6 +1263,7 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
                 fa.variant = bp.fused_variant;
                 fa.rounds = bp.fused_rounds;
                 fa.parity = bp.parity() ? 1 : 0;
+                fa.ring = bp.head;
                 return launch_fused_z(n, fa, bp.tw_full, st);
             }
             case LC_KERNEL_MAC:

@@ -21,8 +21,9 @@ inline int64_t oct_elems(int n) { int64_t h = n / 2 + 1; return h * h * (n / 2 +
 
 bool supported_n(int n);
 
-// Number of workgroups of the forward x pass (rows per WG depends on N);
-// the DC partial array of one slice has this many doubles.
+// Number of workgroups of the forward x pass with an FP32 spectrum (rows per
+// WG depends on N; the row-batched pass at N = 512); the DC partial array of
+// one slice has this many doubles.
 int x_pass_wgs(int n);
 
 // Source grid pointers of a batch of slices (passed by value as a kernel
@@ -121,6 +122,7 @@ struct FusedArgs {
     int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
     int32_t parity;          // 1: spectra in the parity y layout of the half-plane xy shapes
+    int32_t ring = 0;        // lookback slice k is stored in spectrum slot (k + ring) mod K
     // band means mu[band0 + j] = inv_n3 * sum_k g0[k B + band0 + j] sk[k] (the FP64
     // DC mode), reduced by the first workgroup when mu is non-null
     const double *sk = nullptr, *g0 = nullptr;
@@ -166,8 +168,16 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
 hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
                           bool lum_f64, int64_t n_cells, hipStream_t st);
-// sk[k] = sum_w dcpart[k*W + w] (FP64 per-slice input sums; the fused z
-// pass forms the band means from them, FusedArgs::mu)
-hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, hipStream_t st);
+// sk[s] = sum_w dcpart[s*W + w] for slots s < K (FP64 per-slice input sums;
+// the fused z pass forms the band means from them, FusedArgs::mu). A slot
+// whose sum is not finite increments status[0] and lowers status[1] to its
+// lookback index (s - ring) mod K; status starts as {0, INT32_MAX}.
+hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, int *status, int ring, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+// The same sums and check for the plain forms, read from the DC bin of each
+// slot's fully transformed spectrum (spec + s*stride, complex FP64 or FP32):
+// a NaN or infinity anywhere in a slice's sources reaches that bin.
+hipError_t launch_spec_dc(const void *spec, bool f64, int64_t stride, int K, double *sk, int *status, int ring,
+                          hipStream_t st);
 
 }  // namespace lc

@@ -72,6 +72,7 @@ def test_workspace_bytes_scales_with_problem():
     (dict(n=20), "LC_EUNSUPPORTED"),            # factor 5
     (dict(n=6), "LC_EUNSUPPORTED"),             # below 8
     (dict(n=2048), "LC_EUNSUPPORTED"),          # above 1024
+    (dict(n=768), "LC_EUNSUPPORTED"),           # 2^8 3, above the compiled 512
     (dict(m=9), "LC_EUNSUPPORTED"),
     (dict(radii=[0.0, 0.1, 5.0]), "LC_EUNSUPPORTED"),  # self cell straddles slices
     (dict(radii=[0.0, 5.0, 5.0]), "LC_EINVAL"),        # not strictly increasing
@@ -126,6 +127,8 @@ def test_null_handles_and_last_error():
     assert L.lc_step(None, None, None, 0) == lc.LC_EINVAL
     assert L.lc_time_kernel(None, 0, 0, 1, None) == lc.LC_EINVAL
     assert L.lc_get_schedule(None, 0, None) == lc.LC_EINVAL
+    assert L.lc_advance(None, 0, None) == lc.LC_EINVAL
+    assert L.lc_check_sources(None, 0, None) == lc.LC_EINVAL
     assert L.lc_set_schedule(None, 0, None) == lc.LC_EINVAL
     L.lc_destroy(None)          # no-op
 

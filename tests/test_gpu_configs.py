@@ -5,6 +5,8 @@ otherwise), plus graph replay, repeatability and edge cases.
 Tolerances: FP64 form e_max <= 1e-12; FP32 forms e_rms <= 1e-5 (normwise,
 over the full field or the sample); e_max of the FP32 forms <= 1e-4.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -82,7 +84,7 @@ def grid128_ref():
     b = li.grf_128c_24s().boxes[0]
     say("grid128: oracle kernel and spectral route (library FFT)")
     G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
-    S = [li.dense_grid(b.n, c, v).reshape((b.n,) * 3) for c, v in b.sources]
+    S = [oracle.deposit(b.n, c, v) for c, v in b.sources]
     J = oracle.field_fft(lambda k: G[k], lambda k: S[k], b.n_slices, b.n)
     targets = li.sample_cells(2024, b.n, 256)
     JD = oracle.field_direct(G, b.sources, targets)
@@ -106,34 +108,102 @@ def test_grid128_full_grid(grid128_ref, form):
     check(Jg.ravel()[targets], JD, form, "grid128 sampled route D")
 
 
-# --- full-size sampled parity: 256^3 x 40 slices (the benchmark workload) ------------------
+# --- mean of the field: the FP64 DC mode -------------------------------------------------
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "fp32_plain"])
+def test_grid128_mean_is_fp64_dc(grid128_ref, form):
+    """mean(J) = sum_k G^_k(0) S^_k(0) / N^3 (the DC bin of Eq. 13), with
+    G^_k(0) = sum_c G_k(c) and S^_k(0) = sum_c S_k(c) from the oracle. The
+    FP32 form keeps this bin in FP64, so its mean (FP64 output) is right to
+    far below FP32 rounding; the plain FP32 form is held to FP32 rounding."""
+    lc = _lc()
+    b, J, targets, JD = grid128_ref
+    G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
+    S = [oracle.deposit(b.n, c, v) for c, v in b.sources]
+    mu = oracle.mean_field(G, np.stack(S))
+    prec = {"fp64": lc.LC_PREC_FP64, "fp32": lc.LC_PREC_FP32, "fp32_plain": lc.LC_PREC_FP32_PLAIN}[form]
+    Jg = gpu_fields([b], prec, as_points=True, out_dtype=torch.float64)[0][0]
+    rel = abs(Jg.mean() - mu) / mu
+    say(f"grid128 {form} mean rel error {rel:.3e}")
+    assert rel <= {"fp64": 1e-13, "fp32": 1e-9, "fp32_plain": 1e-5}[form]
+
+
+# --- 256^3 x 40 slices (the benchmark workload), on the benchmark's plan --------------------
+# Stored reference: route D with the dense kernel on the 64^3 stride-4
+# sub-lattice (tests/golden/make_golden.py), with the kernel sums G^_k(0).
+
+def _golden(name):
+    import json
+    import os
+    base = os.path.join(os.path.dirname(__file__), "golden", name)
+    meta = json.load(open(base + ".json"))
+    with np.load(base + ".npz", allow_pickle=False) as z:
+        arrays = {k: z[k] for k in z.files}
+    return arrays, meta
+
 
 @pytest.fixture(scope="module")
-def grid256_ref():
+def grid256_golden():
     b = li.points_256c_40s().boxes[0]
-    targets = np.concatenate([li.sample_cells(3033, b.n, 120),
-                              np.array([0, 1, b.n ** 3 - 1], dtype=np.int64)])
-    say("grid256: oracle route D on sampled cells")
-    JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, targets)
-    return b, targets, JD
+    arrays, meta = _golden("grid256_slices40_sublattice4")
+    assert meta["inputs_sha256"] == li.sources_digest(b), "stored reference was computed from other inputs"
+    tg = li.sublattice_cells(b.n, 4)
+    ssum = np.array([math.fsum(v) for _, v in b.sources])
+    mu = float(np.dot(arrays["gsum"], ssum)) / b.n ** 3
+    return b, tg, arrays["J"], mu
+
+
+def _bench_plan_fields(b, precision, out_dtype):
+    """The benchmark's configuration: dense grids resident on the device,
+    autotuned launch shapes (FP32 form), one graph-captured lc_step."""
+    lc = _lc()
+    fused = precision == lc.LC_PREC_FP32
+    plan = lc.Plan([b], precision=precision, use_graph=True, autotune=fused)
+    plan.build_all()
+    gdt = torch.float64 if precision == lc.LC_PREC_FP64 else torch.float32
+    grids = [torch.from_numpy(li.dense_grid(b.n, c, v)).to(gdt).cuda() for c, v in b.sources]
+    outs = [torch.empty((b.n,) * 3, dtype=out_dtype, device="cuda") for _ in b.bands]
+    plan.step(grids, outs)
+    plan.step(grids, outs)     # a replay of the captured graph
+    torch.cuda.synchronize()
+    sched = plan.get_schedule(0)
+    plan.close()
+    return [o.double().cpu().numpy() for o in outs], sched
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
-def test_grid256_sampled(grid256_ref, form):
+def test_grid256_bench_plan_sublattice(grid256_golden, form):
+    """Element by element on the 64^3 stride-4 sub-lattice, with the plan the
+    benchmark times (autotuned shapes, all 40 slices per forward launch,
+    graph replay); FP64 output of the FP32 form also checks the FP64 mean."""
     lc = _lc()
-    b, targets, JD = grid256_ref
+    b, tg, JD, mu = grid256_golden
     prec = lc.LC_PREC_FP64 if form == "fp64" else lc.LC_PREC_FP32
-    say(f"case grid256 {form} (graph-captured step, dense FP32/FP64 grids)")
-    Jg = gpu_fields([b], prec, step=True, use_graph=True)[0][0]
-    check(Jg.ravel()[targets], JD, form, "grid256 sampled")
+    say(f"case grid256 {form} benchmark plan")
+    outs, sched = _bench_plan_fields(b, prec, torch.float32 if form == "fp32" else torch.float64)
+    say(f"grid256 {form} schedule {sched}")
     if form == "fp32":
-        # mean of the field equals sum_k G^_k(0) S^_k(0) / N^3 (FP64 DC mode)
-        say("grid256 fp32 mean")
+        assert sched["push_group"] == b.n_slices
+    check(outs[0].ravel()[tg], JD, form, "grid256 sub-lattice 64^3")
+    if form == "fp64":
+        rel = abs(outs[0].mean() - mu) / mu
+        say(f"grid256 fp64 mean rel error {rel:.3e}")
+        assert rel <= 1e-13
 
 
-def test_grid256_fp32_vs_fp64_full_grid(grid256_ref):
+def test_grid256_fp32_mean_fp64_output(grid256_golden):
     lc = _lc()
-    b, _, _ = grid256_ref
+    b, tg, JD, mu = grid256_golden
+    outs, _ = _bench_plan_fields(b, lc.LC_PREC_FP32, torch.float64)
+    rel = abs(outs[0].mean() - mu) / mu
+    say(f"grid256 fp32 mean rel error {rel:.3e}")
+    assert rel <= 1e-9
+    check(outs[0].ravel()[tg], JD, "fp32", "grid256 sub-lattice 64^3, FP64 output")
+
+
+def test_grid256_fp32_vs_fp64_full_grid(grid256_golden):
+    lc = _lc()
+    b = grid256_golden[0]
     say("case grid256 fp32 vs fp64 full grid")
     J64 = gpu_fields([b], lc.LC_PREC_FP64, step=True)[0][0]
     J32 = gpu_fields([b], lc.LC_PREC_FP32, step=True)[0][0]
@@ -142,34 +212,70 @@ def test_grid256_fp32_vs_fp64_full_grid(grid256_ref):
     assert e_rms <= 1e-5 and e_max <= 1e-4
 
 
-# --- batched bands: 512^3 x 60 slices x 4 bands ---------------------------------------------
+# --- batched bands: 512^3 x 60 slices x 4 bands, Gaussian-field peak sources ----------------
+# Stored reference: route D over the kernel's support, 16^3 stride-32
+# sub-lattice per band.
 
-def test_grid512_bands_sampled():
+def test_grid512_bands_sublattice():
     lc = _lc()
-    say("grid512: generating sources (uniform 1% recipe)")
-    b = li.bands_512c_60s(recipe="uniform").boxes[0]
-    targets = li.sample_cells(4044, b.n, 12)
-    say("case grid512 fp32 4 bands")
-    Js = gpu_fields([b], lc.LC_PREC_FP32, as_points=True)[0]
+    say("grid512: drawing the Gaussian-field peak sources (16 processes)")
+    b = li.bands_512c_60s(procs=16).boxes[0]
+    arrays, meta = _golden("grid512_slices60_bands4_sublattice32")
+    assert meta["inputs_sha256"] == li.sources_digest(b), "stored reference was computed from other inputs"
+    tg = li.sublattice_cells(b.n, 32)
+    say("case grid512 fp32 4 bands, benchmark plan (dense FP32 grids, graph)")
+    plan = lc.Plan([b], precision=lc.LC_PREC_FP32, use_graph=True, autotune=True)
+    plan.build_all()
+    grids = []
+    for c, v in b.sources:
+        # top-1% cells of a field are distinct: the grid is a plain scatter
+        g = torch.zeros(b.n ** 3, dtype=torch.float32, device="cuda")
+        g[torch.from_numpy(c).cuda()] = torch.from_numpy(v).cuda().float()
+        grids.append(g)
+    outs = [torch.empty((b.n,) * 3, dtype=torch.float32, device="cuda") for _ in b.bands]
+    plan.step(grids, outs)
+    torch.cuda.synchronize()
+    plan.close()
+    del grids
     for band in range(4):
-        say(f"grid512 oracle band {band}")
-        JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[band], b.sources,
-                                          targets)
-        check(Js[band].ravel()[targets], JD, "fp32", f"grid512 band {band}")
+        Jg = outs[band].reshape(-1)[torch.from_numpy(tg).cuda()].double().cpu().numpy()
+        check(Jg, arrays["J"][band], "fp32", f"grid512 band {band} sub-lattice 16^3")
 
 
 # --- batched uneven boxes in one captured step ---------------------------------------------
+# Boxes with N <= 128: the whole field against route F (naive DFT).
+# Boxes with N > 128: the 16^3 sub-lattice against the stored route D.
 
-def test_uneven_uneven_boxes_one_step():
+@pytest.fixture(scope="module")
+def uneven_step():
     lc = _lc()
     w = li.uneven_16boxes()
-    boxes = w.boxes
-    say("case uneven fp32 16 boxes, one graph-captured step")
-    Js = gpu_fields(boxes, lc.LC_PREC_FP32, step=True, use_graph=True)
-    for bi, b in enumerate(boxes):
-        t = li.sample_cells([5055, bi], b.n, 8)
-        JD = oracle.field_direct_ondemand(b.n, b.box, b.radii, b.supersample, b.bands[0], b.sources, t)
-        check(Js[bi][0].ravel()[t], JD, "fp32", f"uneven box {bi} N={b.n} K={b.n_slices}")
+    say("case uneven fp32 16 boxes, one graph-captured step (autotuned)")
+    plan = lc.Plan(w.boxes, precision=lc.LC_PREC_FP32, use_graph=True, autotune=True)
+    plan.build_all()
+    grids = [torch.from_numpy(li.dense_grid(b.n, c, v)).float().cuda() for b in w.boxes for c, v in b.sources]
+    outs = [torch.empty((b.n,) * 3, dtype=torch.float32, device="cuda") for b in w.boxes]
+    plan.step(grids, outs)
+    torch.cuda.synchronize()
+    plan.close()
+    return w, [o.double().cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("bi", range(16))
+def test_uneven_box(uneven_step, bi):
+    w, Js = uneven_step
+    b = w.boxes[bi]
+    if b.n <= 128:
+        G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
+        S = np.stack([oracle.deposit(b.n, c, v) for c, v in b.sources])
+        Jr = oracle.field_dft(G, S)
+        check(Js[bi], Jr, "fp32", f"uneven box {bi} N={b.n} K={b.n_slices} full grid vs naive DFT")
+    else:
+        arrays, meta = _golden("uneven16boxes_sublattice16")
+        assert meta["boxes"][str(bi)]["inputs_sha256"] == li.sources_digest(b)
+        tg = li.sublattice_cells(b.n, b.n // 16)
+        check(Js[bi].ravel()[tg], arrays[f"J{bi}"], "fp32",
+              f"uneven box {bi} N={b.n} K={b.n_slices} sub-lattice 16^3")
 
 
 # --- graph replay, repeatability, input forms ---------------------------------------------

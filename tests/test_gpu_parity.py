@@ -36,7 +36,7 @@ def _run_gpu(box, precision, as_points=True, out_dtype=None):
             v = torch.from_numpy(np.asarray(lum, np.float64)).cuda()
             keep.append(plan.push_points(0, k, c, v))
         else:
-            g = torch.from_numpy(oracle.deposit(box.n, cells, lum).ravel()).cuda()
+            g = torch.from_numpy(li.dense_grid(box.n, cells, lum)).cuda()
             if precision != lc.LC_PREC_FP64:
                 g = g.float()
             keep.append(plan.push_grid(0, k, g))

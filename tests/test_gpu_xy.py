@@ -294,7 +294,7 @@ def test_step_with_point_lists_among_dense_grids(form):
             o.fill_(float("nan"))
         keep = plan.step(mixed, outs)
         torch.cuda.synchronize()
-        assert len(keep) == 2
+        assert sum(isinstance(k, tuple) for k in keep) == 2   # the two point lists among the sources
         for o, r in zip(outs, ref):
             d = float((o.double() - r.double()).abs().max())
             sc = float(r.double().abs().max())
