@@ -56,6 +56,9 @@ constexpr size_t kAlign = 256;
 // persistent workgroups of the fused pass can never exceed this (256 CUs x 8)
 constexpr int64_t kMaxParts = 2048;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+// part slots a box's fused pass can use: one per persistent workgroup, and
+// never more workgroups than tiles
+int64_t fused_parts(int n) { return std::min<int64_t>(kMaxParts, fused_tiles(n)); }
 
 // ---- special functions (host, FP64) ---------------------------------------
 
@@ -351,7 +354,7 @@ Layout layout_of(const lc_plan_desc *d) {
         o.sk = take((size_t)K * 8);
         o.status = take(2 * sizeof(int32_t));
         if (d->precision == LC_PREC_FP32) {
-            o.part = take((size_t)2 * kMaxParts * n * fused_cpw(n) * 8);
+            o.part = take((size_t)2 * fused_parts(n) * n * fused_cpw(n) * 8);
             o.split_tab = take((size_t)((B + 1) / 2) * fused_tiles(n) * 4);
         } else {
             o.part = o.split_tab = 0;
@@ -641,8 +644,8 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         if (p->prec == LC_PREC_FP32) {
             bp.part = p->ws + o.part;
             bp.split_tab = (int *)(p->ws + o.split_tab);
-            bp.max_parts = kMaxParts;
-            bp.part_stride = kMaxParts * x.n * fused_cpw(x.n);
+            bp.max_parts = fused_parts(x.n);
+            bp.part_stride = bp.max_parts * x.n * fused_cpw(x.n);
             bp.tiles = fused_tiles(x.n);
             bp.fused_variant = fused_default_variant(x.n, std::min(2, x.n_bands));
         } bp.maxima = (unsigned long long *)(p->ws + o.maxima);
@@ -1344,5 +1347,6 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     p->gkey.clear();   // the next lc_step captures the new launch sequence
     return ok();
 }
+
 
 }  // extern "C"

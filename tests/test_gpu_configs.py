@@ -12,6 +12,7 @@ import pytest
 
 import lc_inputs as li
 import oracle
+from parity_log import record
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -69,6 +70,7 @@ def gpu_fields(boxes, precision, as_points=True, use_graph=False, step=False, ou
 def check(J, Jr, form, label):
     e_max, e_rms = oracle.rel_errors(J, Jr)
     say(f"{label}: {form} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    record(label, form, e_max, e_rms, np.size(Jr))
     if form == "fp64":
         assert e_max <= 1e-12, (label, e_max)
     else:

@@ -9,6 +9,7 @@ import pytest
 
 import lc_inputs as li
 import oracle
+from parity_log import record
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +65,7 @@ def test_grid32_fp64_full_grid():
     Jr, G = _oracle_full(b)
     e_max, e_rms = oracle.rel_errors(J, Jr)
     print(f"grid32 fp64 e_max={e_max:.3e} e_rms={e_rms:.3e} imag={im:.2e}")
+    record("grid32 full grid", "fp64", e_max, e_rms, J.size)
     assert e_max <= 1e-12
     np.testing.assert_allclose(dc, G.sum(axis=(1, 2, 3)), rtol=1e-13)
     assert im <= 1e-14
@@ -98,6 +100,7 @@ def test_grid32_fp32_forms(prec):
     Jr, _ = _oracle_full(b)
     e_max, e_rms = oracle.rel_errors(J, Jr)
     print(f"grid32 {prec} e_max={e_max:.3e} e_rms={e_rms:.3e}")
+    record("grid32 full grid", prec, e_max, e_rms, J.size)
     assert e_rms <= 1e-5
     assert e_max <= 1e-4
 
