@@ -226,6 +226,29 @@ int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t d
  * performs the same check after its copies. */
 int lc_check_sources(lc_plan_t *plan, int32_t box, int32_t *first_bad);
 
+/* Size of the device scratch of lc_step_static, per GPU. */
+#define LC_STATIC_SCRATCH_BYTES (128u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * step of one box - lc_plan, lc_build_greens for every band (atten[b]),
+ * lc_step - with no workspace from the caller and no allocation. The plan's
+ * buffers live in a static device array of LC_STATIC_SCRATCH_BYTES per GPU,
+ * held until the process ends (looked up once per GPU on the first call on
+ * it). desc: one box; workspace NULL, workspace_bytes 0, use_graph 0,
+ * autotune 0 (built-in launch shapes). srcs, out, dtype as lc_step (device
+ * memory). Work is enqueued on desc->hip_stream and the call synchronises
+ * that stream before it returns. Every call on a GPU shares that GPU's
+ * scratch and leaves its contents behind (each call clears what must start
+ * at zero): calls that overlap on one GPU (several host threads, or streams
+ * used by other callers at the same time) race and must be serialised by
+ * the caller. Errors as lc_plan/lc_build_greens/lc_step, plus LC_ENOMEM when
+ * the box needs more than LC_STATIC_SCRATCH_BYTES (lc_workspace_bytes of the
+ * same desc) and LC_EINVAL for a caller workspace, several boxes, graphs or
+ * autotuning. */
+int lc_step_static(const lc_plan_desc *desc, const lc_atten *atten, const lc_sources *srcs, void *const *out,
+                   int32_t dtype);
+
 /* Release the plan's host state and its side streams (no caller memory is
  * freed). NULL is a no-op. */
 void lc_destroy(lc_plan_t *plan);

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", 
 EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance",
             "lc_field", "lc_step", "lc_check_sources", "lc_destroy", "lc_last_error",
             "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
-            "lc_set_schedule"]
+            "lc_set_schedule", "lc_step_static"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
  LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD, LC_KERNEL_YX_INV) = range(10)
@@ -95,6 +95,8 @@ def load():
     L.lc_check_sources.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
     L.lc_field.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_int32]
     L.lc_step.argtypes = [C.c_void_p, C.POINTER(lc_sources), C.POINTER(C.c_void_p), C.c_int32]
+    L.lc_step_static.argtypes = [C.POINTER(lc_plan_desc), C.POINTER(lc_atten), C.POINTER(lc_sources),
+                                 C.POINTER(C.c_void_p), C.c_int32]
     L.lc_destroy.argtypes = [C.c_void_p]
     L.lc_destroy.restype = None
     L.lc_last_error.restype = C.c_char_p
@@ -105,7 +107,7 @@ def load():
     L.lc_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
     for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance", "lc_field", "lc_step",
                  "lc_check_sources", "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel",
-                 "lc_get_schedule", "lc_set_schedule"]:
+                 "lc_get_schedule", "lc_set_schedule", "lc_step_static"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -187,6 +189,19 @@ def lc_step(plan, srcs: Sequence[lc_sources], outs: Sequence[int], dtype: int):
     sarr = (lc_sources * len(srcs))(*srcs)
     oarr = (C.c_void_p * len(outs))(*[C.c_void_p(o) for o in outs])
     _check(load().lc_step(plan, sarr, oarr, dtype))
+
+
+def lc_step_static(desc: lc_plan_desc, attens: Sequence[lc_atten], srcs: Sequence[lc_sources],
+                   outs: Sequence[int], dtype: int):
+    """One whole step of one box with no caller workspace and no allocation
+    (static device scratch; synchronises desc.hip_stream)."""
+    aarr = (lc_atten * len(attens))(*attens)
+    sarr = (lc_sources * len(srcs))(*srcs)
+    oarr = (C.c_void_p * len(outs))(*[C.c_void_p(o) for o in outs])
+    _check(load().lc_step_static(C.byref(desc), aarr, sarr, oarr, dtype))
+
+
+LC_STATIC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
 def lc_destroy(plan):

@@ -1349,4 +1349,79 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
 }
 
 
+// ---- allocation-free whole step (static device scratch) ----------------------
+
+}  // extern "C"
+
+// Device scratch of lc_step_static: one copy per GPU, held until the
+// process ends. Host code never uses this name as an address (on the host it
+// is only a stand-in for the symbol); the device address of each GPU's copy
+// comes from hipGetSymbolAddress with that GPU current.
+static __device__ __align__(256) char scratch[LC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch, looked up on the first call
+// on that GPU.
+int scratch_ptr(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LC_EDEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LC_EDEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lc_step_static(const lc_plan_desc *desc, const lc_atten *atten, const lc_sources *srcs, void *const *out,
+                   int32_t dtype) {
+    if (!desc || !atten || !srcs || !out) return fail(LC_EINVAL, "NULL argument");
+    int rc = validate(desc);
+    if (rc) return rc;
+    if (desc->n_boxes != 1) return fail(LC_EINVAL, "lc_step_static takes one box (n_boxes = %d)", desc->n_boxes);
+    if (desc->workspace || desc->workspace_bytes)
+        return fail(LC_EINVAL, "lc_step_static uses its static scratch: workspace must be NULL and 0 bytes");
+    if (desc->use_graph || desc->autotune)
+        return fail(LC_EINVAL, "lc_step_static runs eagerly with the built-in launch shapes (use_graph = autotune = 0)");
+    const size_t need = layout_of(desc).total;
+    if (need > (size_t)LC_STATIC_SCRATCH_BYTES)
+        return fail(LC_ENOMEM, "this box needs %zu bytes of scratch, above the static maximum of %zu bytes "
+                               "(use lc_plan with a caller workspace)", need, (size_t)LC_STATIC_SCRATCH_BYTES);
+    if ((rc = check_device())) return rc;
+    void *ws = nullptr;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    lc_plan_desc d = *desc;
+    d.workspace = ws;
+    d.workspace_bytes = LC_STATIC_SCRATCH_BYTES;
+    lc_plan_t *p = nullptr;
+    if ((rc = lc_plan(&d, &p))) return rc;
+    const int B = desc->boxes[0].n_bands;
+    for (int b = 0; b < B && !rc; ++b) rc = lc_build_greens(p, 0, b, &atten[b]);
+    if (!rc) rc = lc_step(p, srcs, out, dtype);
+    if (!rc) {
+        // the next call on this GPU reuses the scratch: this one's work
+        // must be done with it first
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) rc = fail(LC_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    }
+    const std::string msg = g_err;
+    lc_destroy(p);
+    if (rc) {
+        g_err = msg;
+        return rc;
+    }
+    return ok();
+}
+
 }  // extern "C"
