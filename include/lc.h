@@ -216,6 +216,58 @@ int lc_field(lc_plan_t *plan, int32_t box, int32_t band, void *const *out,
  * call. Outputs of different boxes must not overlap. */
 int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t dtype);
 
+/* Evaluate the field with the sources frozen at one lookback slice: every
+ * slice k uses the sources of lookback slice `slice` (normally 0, the
+ * observing time) while the kernels G^_{k,b} keep their retarded-time
+ * shells and radial factors - the instantaneously affected field of Sec. 3
+ * (Eq. 18). Same outputs, errors and ordering as lc_field;
+ * LC_EINVAL if slice is outside [0, K) of a selected box. */
+int lc_field_frozen(lc_plan_t *plan, int32_t box, int32_t band, int32_t slice, void *const *out,
+                    int32_t dtype, int32_t mem);
+
+/* Fractional difference of two fields (Sec. 3, the comparison of the
+ * instantaneous and the light-cone field): out[i] = (j_inst[i] - j[i]) / j[i]
+ * where j[i] != 0, else 0. count values of `dtype` (LC_F32/LC_F64) in
+ * device memory, computed in FP64 on hip_stream (NULL: default stream).
+ * out may alias either input. */
+int lc_fdiff(const void *j, const void *j_inst, void *out, int64_t count, int32_t dtype, void *hip_stream);
+
+/* Background cosmology: a flat universe of matter and a cosmological
+ * constant (Omega_L = 1 - omega_m), H0 = 100 h km/s/Mpc. */
+typedef struct {
+    double h;
+    double omega_m;      /* (0, 1] */
+} lc_cosmo;
+
+/* Lookback slices of equal cosmic time dt_myr (Myr) before an observing
+ * redshift z_obs (algorithm step 1 with the conformal time of Eqs. 4-5):
+ * slice k covers cosmic times [t_obs - (k+1) dt, t_obs - k dt]; z_edge[k]
+ * (K+1 values, may be NULL) is the redshift at t_obs - k dt, radii[k] (K+1
+ * values) the comoving distance light travels from it to z_obs, c (tau_obs -
+ * tau_k), in comoving Mpc (radii[0] = 0), and z_src[k] (K values, may be
+ * NULL) the redshift at the slice's middle time t_obs - (k + 1/2) dt.
+ * Host only. Errors: LC_EINVAL (bad cosmology, z_obs < 0, dt <= 0, K
+ * outside [1, 1024], slices reaching t = 0). */
+int lc_cosmo_slices(const lc_cosmo *c, double z_obs, double dt_myr, int32_t K, double *radii, double *z_edge,
+                    double *z_src);
+
+/* Lyman-Werner radial factors of K slices (Sec. 3): for source redshift
+ * z_src[k], alpha_k of Eq. 16, the modulation of Eq. 15 with scale
+ * 116.29 alpha_k and horizon 97.39 alpha_k (kind 2: as printed, hard cut;
+ * kind 1: the continuous form max(0, .), whose zero lies 0.15% beyond the
+ * printed horizon), and prefactor (1+z_obs)^3 / (1+z_src[k]) / (4 pi) so
+ * that the kernel's 1/(4 pi r^2) completes Eq. 14's 1/((4 pi)^2 r^2). r is
+ * in comoving Mpc, so the box length and radii must be too. The factor is
+ * held fixed over each slice at its middle redshift. Host only. */
+int lc_lw_factors(const lc_cosmo *c, double z_obs, int32_t K, const double *z_src, int32_t kind,
+                  lc_atten *out);
+
+/* As lc_build_greens with one radial factor per slice (per_slice[k], K
+ * entries): the dilution factor of Eq. 8 depends on the source time as well
+ * (Eq. 17: (1+z_s) and alpha(z_s)). The self cell of slice 0 uses
+ * per_slice[0]. */
+int lc_build_greens_slices(lc_plan_t *plan, int32_t box, int32_t band, const lc_atten *per_slice);
+
 /* Non-finite source check (LC_ENONFINITE): every field evaluation reduces
  * each slice's sources in FP64 (the sum also gives the FP64 mean of the
  * FP32 form, S^_k(0) of Eq. 13) and flags a slice whose sum is NaN or

@@ -65,6 +65,13 @@ def lib():
         L.or_field_direct_support.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, C.c_int,
                                               ap, ip, ip, dp, C.c_int64, ip, dp]
         L.or_dft3_naive.argtypes = [C.c_int, C.c_int, C.c_void_p]
+        L.or_cosmic_time.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_cosmic_time.restype = C.c_double
+        L.or_comoving_distance.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.or_comoving_distance.restype = C.c_double
+        L.or_redshift_at_time.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_redshift_at_time.restype = C.c_double
+        L.or_build_G_slices.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, ap, C.c_int, dp]
         L.or_dft3_brute.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
         L.or_conv3_brute.argtypes = [C.c_int, dp, dp, dp]
         L.or_num_threads.restype = C.c_int
@@ -137,6 +144,78 @@ def build_G(n: int, L: float, radii, m: int, at, conserve: int = 0) -> np.ndarra
     rc = lib().or_build_G(n, L, K, _dptr(radii), m, C.byref(a), int(conserve), _dptr(G))
     assert rc == 0
     return G
+
+
+def build_G_slices(n: int, L: float, radii, m: int, attens, conserve: int = 0) -> np.ndarray:
+    """Dense G[k] with radial factor attens[k] for slice k (the self cell of
+    slice 0 with attens[0])."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    K = len(radii) - 1
+    assert len(attens) == K
+    G = np.zeros((K, n, n, n))
+    arr = (_Atten * K)(*[_atten(a) for a in attens])
+    rc = lib().or_build_G_slices(n, L, K, _dptr(radii), m, arr, int(conserve), _dptr(G))
+    assert rc == 0
+    return G
+
+
+# --- cosmology (Sec. 2.1 Eqs. 4-5; Sec. 3 Eqs. 14-17) ---------------------------------
+
+def cosmic_time(h: float, om: float, z: float) -> float:
+    """Myr since the big bang at redshift z (flat matter + Lambda)."""
+    return float(lib().or_cosmic_time(h, om, z))
+
+
+def comoving_distance(h: float, om: float, z1: float, z2: float) -> float:
+    """Comoving Mpc that light travels between redshifts z2 and z1 (z1 <= z2)."""
+    return float(lib().or_comoving_distance(h, om, z1, z2))
+
+
+def redshift_at_time(h: float, om: float, t: float) -> float:
+    return float(lib().or_redshift_at_time(h, om, t))
+
+
+def cosmo_slices(h: float, om: float, z_obs: float, dt_myr: float, K: int):
+    """Slices of equal cosmic time before z_obs: radii r_k = c (tau_obs -
+    tau_k) (comoving Mpc, r_0 = 0), edge redshifts z_k at t_obs - k dt and
+    source redshifts at the slices' middle times t_obs - (k + 1/2) dt."""
+    t0 = cosmic_time(h, om, z_obs)
+    z_edge = [z_obs] + [redshift_at_time(h, om, t0 - k * dt_myr) for k in range(1, K + 1)]
+    radii = [0.0] + [comoving_distance(h, om, z_obs, z) for z in z_edge[1:]]
+    z_src = [redshift_at_time(h, om, t0 - (k + 0.5) * dt_myr) for k in range(K)]
+    return np.array(radii), np.array(z_edge), np.array(z_src)
+
+
+class _LWAtten:
+    def __init__(self, kind, s, cut, prefactor):
+        self.kind, self.a, self.s, self.p, self.c, self.cut, self.prefactor = kind, 1.7, s, 0.68, 0.7, cut, prefactor
+
+
+def lw_factors(h: float, om: float, z_obs: float, z_src, kind: int = 2):
+    """Per-slice Lyman-Werner factors: Eq. 16's alpha at each slice's source
+    redshift, Eq. 15's scale and horizon, and Eq. 14's
+    (1+z)^3 / (1+z_s) / (4 pi) (the kernel carries the other 1/(4 pi r^2))."""
+    out = []
+    for zs in z_src:
+        alpha = (h / 0.7) ** -1 * (om / 0.27) ** -0.5 * ((1.0 + zs) / 21.0) ** -0.5
+        out.append(_LWAtten(kind, 116.29 * alpha, 97.39 * alpha, (1.0 + z_obs) ** 3 / (1.0 + zs) / (4.0 * math.pi)))
+    return out
+
+
+def frozen_sources(sources, slice_: int = 0):
+    """The instantaneous field's input (Eq. 18): every slice holds the
+    sources of lookback slice `slice_`."""
+    return [sources[slice_]] * len(sources)
+
+
+def fdiff(J, J_inst):
+    """(J_inst - J) / J elementwise, 0 where J == 0."""
+    J = np.asarray(J, dtype=np.float64)
+    Ji = np.asarray(J_inst, dtype=np.float64)
+    out = np.zeros_like(J)
+    nz = J != 0
+    out[nz] = (Ji[nz] - J[nz]) / J[nz]
+    return out
 
 
 # --- sources ----------------------------------------------------------------------

@@ -477,6 +477,115 @@ int or_field_direct_support(int N, double L, int K, const double *radii, int m, 
     return 0;
 }
 
+/* ---- background cosmology (Sec. 2.1 Eqs. 4-5) --------------------------
+ * Flat universe of matter and a cosmological constant, OL = 1 - Om,
+ * H(a) = H0 sqrt(Om a^-3 + OL). Units: Myr (Julian year), comoving Mpc,
+ * c = 299792.458 km/s. Every quantity is its defining integral, evaluated
+ * by tanh-sinh quadrature (no closed forms here: the tests compare with them). */
+
+static const double OR_C_KMS = 299792.458;
+static const double OR_MPC_KM = 3.0856775814913673e19;
+static const double OR_MYR_S = 3.15576e13;
+
+typedef double (*or_fn)(double x, const double *par);
+
+/* tanh-sinh quadrature of f over [lo, hi], levels refined until two agree */
+static double tanh_sinh(or_fn f, const double *par, double lo, double hi)
+{
+    if (!(hi > lo)) return 0.0;
+    double prev = 0.0, half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    for (int level = 3; level <= 12; ++level) {
+        double hstep = ldexp(1.0, -level), sum = 0.0;
+        for (int i = -(int)(4.0 / hstep); i <= (int)(4.0 / hstep); ++i) {
+            double t = i * hstep;
+            double u = 0.5 * OR_PI * sinh(t);
+            double ch = cosh(u);
+            double w = 0.5 * OR_PI * cosh(t) / (ch * ch);
+            double x = mid + half * tanh(u);
+            if (!(x > lo) || !(x < hi) || w == 0.0) continue;
+            sum += w * f(x, par);
+        }
+        double est = half * hstep * sum;
+        if (level > 3 && fabs(est - prev) <= 1e-15 * fabs(est)) return est;
+        prev = est;
+    }
+    return prev;
+}
+
+/* dt/da = 1 / (a H(a)), in Myr per unit a; par = {Om, OL, H0 [1/Myr]} */
+static double dt_da(double a, const double *par)
+{
+    return 1.0 / (a * par[2] * sqrt(par[0] / (a * a * a) + par[1]));
+}
+
+/* c / H(z) in Mpc; par = {Om, OL, c/H0 [Mpc]} */
+static double c_over_H(double z, const double *par)
+{
+    double zp = 1.0 + z;
+    return par[2] / sqrt(par[0] * zp * zp * zp + par[1]);
+}
+
+/* cosmic time at redshift z (Myr): t = int_0^{1/(1+z)} da / (a H(a)) */
+double or_cosmic_time(double h, double om, double z)
+{
+    double par[3] = { om, 1.0 - om, 100.0 * h / OR_MPC_KM * OR_MYR_S };
+    return tanh_sinh(dt_da, par, 0.0, 1.0 / (1.0 + z));
+}
+
+/* comoving distance between z1 <= z2 (Mpc): int_{z1}^{z2} c dz / H(z) */
+double or_comoving_distance(double h, double om, double z1, double z2)
+{
+    double par[3] = { om, 1.0 - om, OR_C_KMS / (100.0 * h) };
+    return tanh_sinh(c_over_H, par, z1, z2);
+}
+
+/* redshift at cosmic time t (Myr), by bisection on the monotone t(z) */
+double or_redshift_at_time(double h, double om, double t)
+{
+    double lo = 0.0, hi = 1.0;
+    while (or_cosmic_time(h, om, hi) > t) hi *= 2.0;      /* t decreases with z */
+    if (or_cosmic_time(h, om, lo) < t) return -1.0;        /* later than z = 0 */
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+        double m = 0.5 * (lo + hi);
+        if (or_cosmic_time(h, om, m) > t) lo = m; else hi = m;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Dense kernel with one radial factor per slice: G[k] uses at[k] (the
+ * self cell of slice 0 with at[0]). */
+int or_build_G_slices(int N, double L, int K, const double *radii, int m,
+                      const or_atten *at, int conserve, double *G)
+{
+    const int64_t n3 = (int64_t)N * N * N;
+    memset(G, 0, sizeof(double) * n3 * K);
+    for (int k = 0; k < K; ++k) {
+        kern_t kp;
+        if (kern_init(&kp, N, L, K, radii, m, &at[k])) return -1;
+        double *Gk = G + (int64_t)k * n3;
+        #pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t c = 0; c < n3; ++c) {
+            int i = (int)(c / ((int64_t)N * N)), j = (int)((c / N) % N), x = (int)(c % N);
+            double v = 0.0;
+            kern_accumulate(&kp, i, j, x, k, k + 1, &v);
+            Gk[c] = v;
+        }
+        if (conserve) {
+            double l3 = kp.l * kp.l * kp.l, s = 0.0, comp = 0.0;
+            for (int64_t c = 0; c < n3; ++c) {
+                double v = Gk[c], t = s + v;
+                comp += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
+                s = t;
+            }
+            s += comp;
+            double target = or_shell_integral(&at[k], radii[k], radii[k + 1]);
+            double f = (s != 0.0) ? target / (l3 * s) : 0.0;
+            for (int64_t c = 0; c < n3; ++c) Gk[c] *= f;
+        }
+    }
+    return 0;
+}
+
 /* ---- naive DFT (Eq. 12 convention) ------------------------------------- */
 
 /* Twiddle table e^{sign 2 pi i j / N}, j in [0, N), from long double libm. */

@@ -31,7 +31,8 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_EINVAL", -2: "LC_ENOMEM", -3: "LC_EDEVICE", 
 EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance",
             "lc_field", "lc_step", "lc_check_sources", "lc_destroy", "lc_last_error",
             "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
-            "lc_set_schedule", "lc_step_static"]
+            "lc_set_schedule", "lc_step_static", "lc_field_frozen", "lc_fdiff", "lc_cosmo_slices",
+            "lc_lw_factors", "lc_build_greens_slices"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
  LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD, LC_KERNEL_YX_INV) = range(10)
@@ -59,6 +60,10 @@ class lc_atten(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a", C.c_double),
                 ("s", C.c_double), ("p", C.c_double), ("c", C.c_double), ("cut", C.c_double),
                 ("prefactor", C.c_double)]
+
+
+class lc_cosmo(C.Structure):
+    _fields_ = [("h", C.c_double), ("omega_m", C.c_double)]
 
 
 class lc_sources(C.Structure):
@@ -97,6 +102,13 @@ def load():
     L.lc_step.argtypes = [C.c_void_p, C.POINTER(lc_sources), C.POINTER(C.c_void_p), C.c_int32]
     L.lc_step_static.argtypes = [C.POINTER(lc_plan_desc), C.POINTER(lc_atten), C.POINTER(lc_sources),
                                  C.POINTER(C.c_void_p), C.c_int32]
+    L.lc_field_frozen.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                  C.c_int32, C.c_int32]
+    L.lc_fdiff.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    dp = C.POINTER(C.c_double)
+    L.lc_cosmo_slices.argtypes = [C.POINTER(lc_cosmo), C.c_double, C.c_double, C.c_int32, dp, dp, dp]
+    L.lc_lw_factors.argtypes = [C.POINTER(lc_cosmo), C.c_double, C.c_int32, dp, C.c_int32, C.POINTER(lc_atten)]
+    L.lc_build_greens_slices.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_atten)]
     L.lc_destroy.argtypes = [C.c_void_p]
     L.lc_destroy.restype = None
     L.lc_last_error.restype = C.c_char_p
@@ -107,7 +119,8 @@ def load():
     L.lc_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(lc_schedule)]
     for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance", "lc_field", "lc_step",
                  "lc_check_sources", "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel",
-                 "lc_get_schedule", "lc_set_schedule", "lc_step_static"]:
+                 "lc_get_schedule", "lc_set_schedule", "lc_step_static", "lc_field_frozen", "lc_fdiff",
+                 "lc_cosmo_slices", "lc_lw_factors", "lc_build_greens_slices"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -202,6 +215,46 @@ def lc_step_static(desc: lc_plan_desc, attens: Sequence[lc_atten], srcs: Sequenc
 
 
 LC_STATIC_SCRATCH_BYTES = 128 * 1024 * 1024
+
+
+def lc_cosmo_slices(h: float, omega_m: float, z_obs: float, dt_myr: float, K: int):
+    """Lookback slicing by cosmic time (host only): (radii[K+1] comoving Mpc,
+    z_edge[K+1], z_src[K]) as numpy arrays."""
+    import numpy as np
+    c = lc_cosmo(float(h), float(omega_m))
+    r = (C.c_double * (K + 1))()
+    ze = (C.c_double * (K + 1))()
+    zs = (C.c_double * K)()
+    _check(load().lc_cosmo_slices(C.byref(c), float(z_obs), float(dt_myr), int(K), r, ze, zs))
+    return np.array(r[:]), np.array(ze[:]), np.array(zs[:])
+
+
+def lc_lw_factors(h: float, omega_m: float, z_obs: float, z_src, kind: int = 2):
+    """Per-slice Lyman-Werner radial factors (host only): list of lc_atten."""
+    K = len(z_src)
+    c = lc_cosmo(float(h), float(omega_m))
+    zs = (C.c_double * K)(*[float(v) for v in z_src])
+    out = (lc_atten * K)()
+    _check(load().lc_lw_factors(C.byref(c), float(z_obs), K, zs, int(kind), out))
+    return [out[k] for k in range(K)]
+
+
+def fdiff(j, j_inst, out=None):
+    """(j_inst - j) / j elementwise on the device (lc_fdiff; 0 where j == 0)."""
+    import torch
+    if j.shape != j_inst.shape or j.dtype != j_inst.dtype:
+        raise ValueError("fdiff: fields of one shape and dtype required")
+    a = check_tensor(j, "j", dtypes=(torch.float32, torch.float64), device=j.device)
+    b = check_tensor(j_inst, "j_inst", dtypes=(torch.float32, torch.float64), numel=a.numel(), device=a.device)
+    if not a.is_cuda:
+        raise ValueError("fdiff: device tensors required")
+    if out is None:
+        out = torch.empty_like(a)
+    out = check_tensor(out, "out", dtypes=(a.dtype,), numel=a.numel(), device=a.device, copy_ok=False)
+    st = torch.cuda.current_stream(a.device).cuda_stream
+    _check(load().lc_fdiff(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr()),
+                           a.numel(), LC_F64 if a.dtype == torch.float64 else LC_F32, C.c_void_p(st)))
+    return out
 
 
 def lc_destroy(plan):
@@ -320,6 +373,16 @@ class Plan:
         at = atten if atten is not None else self.boxes[box].bands[band]
         self._call(lc_build_greens, self.handle, box, band, make_atten(at))
 
+    def build_greens_slices(self, box: int, band: int, attens):
+        """One radial factor per slice (lc_build_greens_slices): attens is a
+        sequence of K objects with kind, a, s, p, c, cut, prefactor (or
+        lc_atten structs)."""
+        K = len(self.boxes[box].radii) - 1
+        if len(attens) != K:
+            raise ValueError(f"build_greens_slices takes {K} radial factors, got {len(attens)}")
+        arr = (lc_atten * K)(*[a if isinstance(a, lc_atten) else make_atten(a) for a in attens])
+        self._call(lambda: _check(load().lc_build_greens_slices(self.handle, box, band, arr)))
+
     def build_all(self):
         for bi, b in enumerate(self.boxes):
             for band in range(len(b.bands)):
@@ -402,6 +465,22 @@ class Plan:
         dt = LC_F64 if out.dtype == torch.float64 else LC_F32
         mem = LC_MEM_DEVICE if out.is_cuda else LC_MEM_HOST
         self._call(lc_field, self.handle, box, band, [out.data_ptr()], dt, mem)
+        return out
+
+    def field_frozen(self, box: int = 0, band: int = 0, slice_: int = 0, dtype=None, out=None):
+        """The instantaneous field (lc_field_frozen): every slice uses the
+        sources of lookback slice `slice_`."""
+        torch = self.torch
+        n = self._box_n(box)
+        dtype = dtype or (torch.float64 if self.precision == LC_PREC_FP64 else torch.float32)
+        if out is None:
+            out = torch.empty((n, n, n), dtype=dtype, device=self.device)
+        out = check_tensor(out, "output field", dtypes=(torch.float32, torch.float64), numel=n ** 3,
+                           device=self.device, allow_host=True, copy_ok=False)
+        dt = LC_F64 if out.dtype == torch.float64 else LC_F32
+        mem = LC_MEM_DEVICE if out.is_cuda else LC_MEM_HOST
+        arr = (C.c_void_p * 1)(C.c_void_p(out.data_ptr()))
+        self._call(lambda: _check(load().lc_field_frozen(self.handle, box, band, slice_, arr, dt, mem)))
         return out
 
     def greens_dc(self, box: int = 0, band: int = 0):

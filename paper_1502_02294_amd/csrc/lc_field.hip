@@ -97,6 +97,7 @@ struct FusedDev {
     double *mu;
     int32_t K;
     int32_t ring;              // lookback k lives in spectrum slot (k + ring) mod K
+    int32_t frozen;            // >= 0: every lookback slice reads slot `frozen` (instantaneous field)
 };
 
 // Processing order of the main tiles in the rounds schedule. Main tile
@@ -175,7 +176,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         for (int b = 0; b < NB_; ++b) {
             double v = 0.0;
             for (int k = threadIdx.x; k < a.K; k += 64) {
-                const int slot = k + a.ring < a.K ? k + a.ring : k + a.ring - a.K;
+                const int slot = a.frozen >= 0 ? a.frozen : (k + a.ring < a.K ? k + a.ring : k + a.ring - a.K);
                 v += a.g0[(int64_t)k * a.B + a.band0 + b] * a.sk[slot];
             }
             for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -261,6 +262,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         auto spec_at = [&](int k) {
             int slot = (k < k1 ? k : k1 - 1) + a.ring;
             if (slot >= a.K) slot -= a.K;
+            if (a.frozen >= 0) slot = a.frozen;
             return (const char *)(a.spec + (int64_t)slot * a.spec_stride);
         };
         // first-pass inputs of the next PF slices, kept in flight in a ring of
@@ -658,7 +660,7 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
     d.kmax = kmax; d.P = (int32_t)P; d.W = tiles * kmax;
     d.rounds = fa.rounds; d.tiles = tiles;
-    d.sk = fa.sk; d.g0 = fa.g0; d.inv_n3 = fa.inv_n3; d.mu = fa.mu; d.K = fa.K; d.ring = fa.ring;
+    d.sk = fa.sk; d.g0 = fa.g0; d.inv_n3 = fa.inv_n3; d.mu = fa.mu; d.K = fa.K; d.ring = fa.ring; d.frozen = fa.frozen;
     // the split table serves the stream-K mode's merge in the inverse y pass;
     // the rounds mode splits no tile and its inverse pass does not read it
     if (!fa.rounds)

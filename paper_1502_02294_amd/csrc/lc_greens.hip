@@ -184,6 +184,28 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void fdiff_kernel(const T *__restrict__ j, const T *__restrict__ ji,
+                                                    T *__restrict__ out, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)j[e], b = (double)ji[e];
+        out[e] = (T)(a != 0.0 ? (b - a) / a : 0.0);
+    }
+}
+
+hipError_t launch_fdiff(const void *j, const void *j_inst, void *out, int64_t count, bool f64, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);
+    if (f64)
+        hipLaunchKernelGGL(fdiff_kernel<double>, dim3(wgs), dim3(256), 0, st, (const double *)j,
+                           (const double *)j_inst, (double *)out, count);
+    else
+        hipLaunchKernelGGL(fdiff_kernel<float>, dim3(wgs), dim3(256), 0, st, (const float *)j,
+                           (const float *)j_inst, (float *)out, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);

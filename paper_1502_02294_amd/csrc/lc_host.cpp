@@ -739,28 +739,34 @@ void lc_destroy(lc_plan_t *p) {
 
 const char *lc_last_error(void) { return g_err.c_str(); }
 
-int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at) {
-    if (!p) return fail(LC_EINVAL, "plan is NULL");
-    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
-    BoxPlan &bp = p->boxes[box];
-    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range", band);
-    if (!at) return fail(LC_EINVAL, "atten is NULL");
-    if (at->reserved != 0) return fail(LC_EINVAL, "atten.reserved must be 0");
-    if (at->kind < 0 || at->kind > 2) return fail(LC_EINVAL, "unknown atten kind %d", at->kind);
-    if (!std::isfinite(at->prefactor)) return fail(LC_EINVAL, "prefactor must be finite");
+}  // extern "C"
+
+namespace {
+
+int check_atten(const lc_atten *at, int k) {
+    if (at->reserved != 0) return fail(LC_EINVAL, "atten %d: reserved must be 0", k);
+    if (at->kind < 0 || at->kind > 2) return fail(LC_EINVAL, "atten %d: unknown kind %d", k, at->kind);
+    if (!std::isfinite(at->prefactor)) return fail(LC_EINVAL, "atten %d: prefactor must be finite", k);
     if (at->kind != 0) {
         if (!(at->a > 0) || !(at->s > 0) || !(at->p > 0) || !std::isfinite(at->c) || !std::isfinite(at->a) ||
             !std::isfinite(at->s) || !std::isfinite(at->p))
-            return fail(LC_EINVAL, "atten needs finite a, s, p > 0 and finite c");
+            return fail(LC_EINVAL, "atten %d needs finite a, s, p > 0 and finite c", k);
         if (at->kind == 2 && !(at->cut >= 0 && std::isfinite(at->cut)))
-            return fail(LC_EINVAL, "atten kind 2 needs a finite cut >= 0");
+            return fail(LC_EINVAL, "atten %d: kind 2 needs a finite cut >= 0", k);
     }
-    const Atten A = atten_of(at);
+    return LC_OK;
+}
+
+// Kernels of one (box, band), slice k with radial factor A[k] (algorithm
+// steps 2-3). Slices past the last one whose shell meets its factor's
+// support are skipped by the slice sum (kcount).
+int build_impl(lc_plan_t *p, BoxPlan &bp, int band, const std::vector<Atten> &A) {
     const int n = bp.n, K = bp.K;
-    const double end = support_end(A);
     int kc = 0;
-    while (kc < K && bp.radii[kc] < end) ++kc;
-    const double self = bp.radii[0] == 0.0 ? self_cell(A, bp.l) : 0.0;
+    for (int k = 0; k < K; ++k)
+        if (bp.radii[k] < support_end(A[k]) && A[k].pref != 0.0) kc = k + 1;
+    // the unit source's own cell belongs to slice 0 (r_0 = 0)
+    const double self = bp.radii[0] == 0.0 ? self_cell(A[0], bp.l) : 0.0;
     const double l3 = bp.l * bp.l * bp.l;
     const int U = (int)std::ceil(bp.radii[K] / bp.L) + 1;
     const bool oct_f64 = p->t_f64;
@@ -771,7 +777,7 @@ int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at)
     for (int k = 0; k < K; ++k) {
         char *oct = bp.ghat + ((size_t)k * bp.B + band) * oct_elems(n) * rs;
         double *dc = bp.ghat0 + (size_t)k * bp.B + band;
-        if (k >= kc) {
+        if (k >= kc || !(bp.radii[k] < support_end(A[k])) || A[k].pref == 0.0) {
             HIPCHK(launch_fill_bytes(oct, oct_elems(n) * rs, st));
             HIPCHK(launch_fill_f64(dc, 1, 0.0, st));
             continue;
@@ -784,13 +790,14 @@ int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at)
         a.images = U;
         a.self_pair = bp.radii[0] == 0.0 ? 1 : 0;
         a.self_val = (k == 0) ? self : 0.0;
-        a.kind = A.kind; a.a = A.a; a.s = A.s; a.p = A.p; a.c = A.c; a.cut = A.cut; a.pref = A.pref;
+        a.kind = A[k].kind; a.a = A[k].a; a.s = A[k].s; a.p = A[k].p; a.c = A[k].c; a.cut = A[k].cut;
+        a.pref = A[k].pref;
         HIPCHK(launch_greens_build(a, st));
         HIPCHK(launch_x_fwd(n, true, p->scratch_real, true, p->scratch_spec, bp.tw64_half, bp.twist64,
                             nullptr, st));
         HIPCHK(launch_col(n, true, 1, true, p->scratch_spec, bp.tw64_full, st));
         HIPCHK(launch_col(n, true, 2, true, p->scratch_spec, bp.tw64_full, st));
-        const double target = bp.conserve ? (Phi(A, bp.radii[k + 1]) - Phi(A, bp.radii[k])) / l3 : 0.0;
+        const double target = bp.conserve ? (Phi(A[k], bp.radii[k + 1]) - Phi(A[k], bp.radii[k])) / l3 : 0.0;
         HIPCHK(launch_greens_fold(n, p->scratch_spec, oct, oct_f64, bp.conserve, target, dc,
                                   bp.maxima + 2 * band, st));
     }
@@ -799,7 +806,39 @@ int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at)
     // a captured step holds this band's slice count (launch shapes of the
     // slice sum): the next lc_step captures again
     p->gkey.clear();
-    return ok();
+    return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lc_build_greens(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *at) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range", band);
+    if (!at) return fail(LC_EINVAL, "atten is NULL");
+    int rc = check_atten(at, 0);
+    if (rc) return rc;
+    rc = build_impl(p, bp, band, std::vector<Atten>(bp.K, atten_of(at)));
+    return rc ? rc : ok();
+}
+
+int lc_build_greens_slices(lc_plan_t *p, int32_t box, int32_t band, const lc_atten *per_slice) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range", band);
+    if (!per_slice) return fail(LC_EINVAL, "per_slice is NULL");
+    std::vector<Atten> A(bp.K);
+    for (int k = 0; k < bp.K; ++k) {
+        int rc = check_atten(&per_slice[k], k);
+        if (rc) return rc;
+        A[k] = atten_of(&per_slice[k]);
+    }
+    int rc = build_impl(p, bp, band, A);
+    return rc ? rc : ok();
 }
 
 // Stage lookback slice `slice` of a box (its ring slot) on the plan's stream.
@@ -886,7 +925,10 @@ int lc_advance(lc_plan_t *p, int32_t box, const lc_sources *s) {
 }
 
 // Field of one box for bands [b0, b1) into device pointers outp[b - b0].
-static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64, hipStream_t st) {
+// frozen >= 0: every lookback slice reads the sources of ring slot `frozen`
+// (the instantaneous field of Eq. 18).
+static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, bool out_f64, hipStream_t st,
+                     int frozen = -1) {
     BoxPlan &bp = p->boxes[box];
     const int n = bp.n, K = bp.K;
     const size_t cs = p->t_f64 ? 16 : 8;
@@ -915,6 +957,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             fa.parity = bp.parity() ? 1 : 0;
             fa.ring = bp.head;
+            fa.frozen = frozen;
             fa.sk = bp.sk; fa.g0 = bp.ghat0; fa.inv_n3 = inv_n3; fa.mu = bp.mu;
             HIPCHK(launch_fused_z(n, fa, bp.tw_full, st));
             for (int j = 0; j < nb; ++j) {
@@ -939,7 +982,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             const int kc = bp.kcount[b];
             if (kc == 0) HIPCHK(launch_fill_bytes(acc, se * cs, st));
             for (int k = 0; k < kc; ++k)
-                HIPCHK(launch_mac_plain(n, p->t_f64, acc, bp.spec + (size_t)bp.slot(k) * se * cs,
+                HIPCHK(launch_mac_plain(n, p->t_f64, acc, bp.spec + (size_t)(frozen >= 0 ? frozen : bp.slot(k)) * se * cs,
                                         bp.ghat + ((size_t)k * bp.B + b) * oct_elems(n) * rs, k == 0, st));
             HIPCHK(launch_col(n, p->t_f64, 2, false, acc, bp.tw_full, st));
             HIPCHK(launch_col(n, p->t_f64, 1, false, acc, bp.tw_full, st));
@@ -973,7 +1016,8 @@ static int take_status(lc_plan_t *p, int x0, int x1, int32_t *first_bad) {
     return code;
 }
 
-int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t dtype, int32_t mem) {
+static int field_impl(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t dtype, int32_t mem,
+                      int frozen_lookback) {
     if (!p) return fail(LC_EINVAL, "plan is NULL");
     if (!out) return fail(LC_EINVAL, "out is NULL");
     if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad output dtype");
@@ -986,6 +1030,8 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
         const BoxPlan &bp = p->boxes[x];
         if (band < -1 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range for box %d", band, x);
         const int b0 = band < 0 ? 0 : band, b1 = band < 0 ? bp.B : band + 1;
+        if (frozen_lookback >= bp.K)
+            return fail(LC_EINVAL, "frozen slice %d out of range for box %d (K = %d)", frozen_lookback, x, bp.K);
         for (int b = b0; b < b1; ++b) {
             if (!bp.built[b]) return fail(LC_ESTATE, "kernel of box %d band %d not built", x, b);
             if (!out[nout]) return fail(LC_EINVAL, "output pointer %zu is NULL", nout);
@@ -997,14 +1043,15 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
     for (int x = x0; x < x1; ++x) {
         BoxPlan &bp = p->boxes[x];
         const int b0 = band < 0 ? 0 : band, b1 = band < 0 ? bp.B : band + 1;
+        const int frozen = frozen_lookback >= 0 ? bp.slot(frozen_lookback) : -1;
         if (mem == LC_MEM_DEVICE) {
-            int rc = field_box(p, x, b0, b1, out + o, f64, p->stream);
+            int rc = field_box(p, x, b0, b1, out + o, f64, p->stream, frozen);
             if (rc) return rc;
         } else {
             const size_t bytes = (size_t)bp.n * bp.n * bp.n * (f64 ? 8 : 4);
             for (int b = b0; b < b1; ++b) {
                 void *dev = p->scratch_real;
-                int rc = field_box(p, x, b, b + 1, &dev, f64, p->stream);
+                int rc = field_box(p, x, b, b + 1, &dev, f64, p->stream, frozen);
                 if (rc) return rc;
                 HIPCHK(hipMemcpyAsync(out[o + (b - b0)], dev, bytes, hipMemcpyDeviceToHost, p->stream));
                 HIPCHK(hipStreamSynchronize(p->stream));
@@ -1017,6 +1064,24 @@ int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t 
         int rc = take_status(p, x0, x1, nullptr);
         if (rc) return rc;
     }
+    return ok();
+}
+
+int lc_field(lc_plan_t *p, int32_t box, int32_t band, void *const *out, int32_t dtype, int32_t mem) {
+    return field_impl(p, box, band, out, dtype, mem, -1);
+}
+
+int lc_field_frozen(lc_plan_t *p, int32_t box, int32_t band, int32_t slice, void *const *out, int32_t dtype,
+                    int32_t mem) {
+    if (slice < 0) return fail(LC_EINVAL, "frozen slice %d must be >= 0", slice);
+    return field_impl(p, box, band, out, dtype, mem, slice);
+}
+
+int lc_fdiff(const void *j, const void *j_inst, void *out, int64_t count, int32_t dtype, void *hip_stream) {
+    if (count < 0) return fail(LC_EINVAL, "count must be >= 0");
+    if (count > 0 && (!j || !j_inst || !out)) return fail(LC_EINVAL, "NULL field pointer");
+    if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad dtype");
+    HIPCHK(launch_fdiff(j, j_inst, out, count, dtype == LC_F64, (hipStream_t)hip_stream));
     return ok();
 }
 
@@ -1348,6 +1413,126 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     return ok();
 }
 
+
+// ---- cosmological slicing and Lyman-Werner radial factors ---------------------
+//
+// Flat universe of matter and a cosmological constant (Omega_L = 1 - Omega_m):
+//  * cosmic time, closed form: t(z) = 2 / (3 H0 sqrt(OL)) asinh(sqrt(OL/Om) (1+z)^-1.5)
+//    (the matter-only limit 2 / (3 H0 sqrt(Om)) (1+z)^-1.5 when OL = 0);
+//  * conformal distance (Eq. 5 times c): chi(z1, z2) = (c/H0) int dz / E(z),
+//    E = sqrt(Om (1+z)^3 + OL); with u = (1+z)^-1/2 the integrand becomes
+//    2 / sqrt(Om + OL u^6), smooth on [u2, u1], integrated by Gauss-Legendre.
+// Units: Myr (Julian year), comoving Mpc, c = 299792.458 km/s.
+
+}  // extern "C"
+
+namespace {
+
+constexpr double kC_kms = 299792.458;
+constexpr double kMpc_km = 3.0856775814913673e19;
+constexpr double kMyr_s = 3.15576e13;
+
+struct Bg {
+    double om, ol, H0_myr, dh_mpc;
+};
+
+int bg_of(const lc_cosmo *c, Bg *b) {
+    if (!c) return fail(LC_EINVAL, "cosmology is NULL");
+    if (!(c->h > 0) || !std::isfinite(c->h)) return fail(LC_EINVAL, "h must be > 0");
+    if (!(c->omega_m > 0 && c->omega_m <= 1)) return fail(LC_EINVAL, "omega_m must be in (0, 1]");
+    b->om = c->omega_m;
+    b->ol = 1.0 - c->omega_m;
+    b->H0_myr = 100.0 * c->h / kMpc_km * kMyr_s;
+    b->dh_mpc = kC_kms / (100.0 * c->h);
+    return LC_OK;
+}
+
+double t_of_z(const Bg &b, double z) {
+    const double x = std::pow(1.0 + z, -1.5);
+    if (b.ol <= 0.0) return 2.0 / (3.0 * b.H0_myr * std::sqrt(b.om)) * x;
+    return 2.0 / (3.0 * b.H0_myr * std::sqrt(b.ol)) * std::asinh(std::sqrt(b.ol / b.om) * x);
+}
+
+double z_of_t(const Bg &b, double t) {
+    double x;
+    if (b.ol <= 0.0) x = 1.5 * b.H0_myr * std::sqrt(b.om) * t;
+    else x = std::sqrt(b.om / b.ol) * std::sinh(1.5 * b.H0_myr * std::sqrt(b.ol) * t);
+    return std::pow(x, -2.0 / 3.0) - 1.0;
+}
+
+struct Rule32 {
+    std::vector<double> x, w;
+    Rule32() { gauss01(32, x, w); }
+};
+
+double chi(const Bg &b, double z1, double z2) {
+    static const Rule32 rule;    // built once (thread-safe static initialisation)
+    const std::vector<double> &gx = rule.x, &gw = rule.w;
+    const double u1 = 1.0 / std::sqrt(1.0 + z1), u2 = 1.0 / std::sqrt(1.0 + z2);
+    // four panels over [u2, u1]
+    double acc = 0.0;
+    for (int pnl = 0; pnl < 4; ++pnl) {
+        const double a = u2 + (u1 - u2) * pnl / 4.0, w = (u1 - u2) / 4.0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            const double u = a + w * gx[i];
+            const double u3 = u * u * u;
+            acc += gw[i] * w * 2.0 / std::sqrt(b.om + b.ol * u3 * u3);
+        }
+    }
+    return b.dh_mpc * acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lc_cosmo_slices(const lc_cosmo *c, double z_obs, double dt_myr, int32_t K, double *radii, double *z_edge,
+                    double *z_src) {
+    Bg b;
+    int rc = bg_of(c, &b);
+    if (rc) return rc;
+    if (!(z_obs >= 0) || !std::isfinite(z_obs)) return fail(LC_EINVAL, "z_obs must be finite and >= 0");
+    if (!(dt_myr > 0) || !std::isfinite(dt_myr)) return fail(LC_EINVAL, "dt_myr must be > 0");
+    if (K < 1 || K > 1024) return fail(LC_EINVAL, "K must be in [1, 1024]");
+    if (!radii) return fail(LC_EINVAL, "radii is NULL");
+    const double t0 = t_of_z(b, z_obs);
+    if (!(t0 - K * dt_myr > 0.0))
+        return fail(LC_EINVAL, "K = %d slices of %g Myr reach beyond t = 0 (t_obs = %g Myr)", K, dt_myr, t0);
+    for (int k = 0; k <= K; ++k) {
+        const double zk = k == 0 ? z_obs : z_of_t(b, t0 - k * dt_myr);
+        radii[k] = k == 0 ? 0.0 : chi(b, z_obs, zk);
+        if (z_edge) z_edge[k] = zk;
+        if (z_src && k < K) z_src[k] = z_of_t(b, t0 - (k + 0.5) * dt_myr);
+    }
+    return ok();
+}
+
+int lc_lw_factors(const lc_cosmo *c, double z_obs, int32_t K, const double *z_src, int32_t kind, lc_atten *out) {
+    Bg b;
+    int rc = bg_of(c, &b);
+    if (rc) return rc;
+    if (K < 1 || !z_src || !out) return fail(LC_EINVAL, "K >= 1 and non-NULL z_src, out required");
+    if (kind != 1 && kind != 2) return fail(LC_EINVAL, "kind must be 1 (continuous) or 2 (Eq. 15 as printed)");
+    const double pi = 3.141592653589793238462643383279502884;
+    for (int k = 0; k < K; ++k) {
+        if (!(z_src[k] >= z_obs) || !std::isfinite(z_src[k]))
+            return fail(LC_EINVAL, "z_src[%d] = %g must be finite and >= z_obs", k, z_src[k]);
+        // Eq. 16
+        const double alpha = std::pow(c->h / 0.7, -1.0) * std::pow(c->omega_m / 0.27, -0.5) *
+                             std::pow((1.0 + z_src[k]) / 21.0, -0.5);
+        lc_atten &a = out[k];
+        a.kind = kind;
+        a.reserved = 0;
+        a.a = 1.7;               // Eq. 15
+        a.s = 116.29 * alpha;
+        a.p = 0.68;
+        a.c = 0.7;
+        a.cut = 97.39 * alpha;
+        // Eq. 14: (1/(4 pi)^2) (1+z)^3 / (1+z_s); the kernel carries 1/(4 pi r^2)
+        a.prefactor = std::pow(1.0 + z_obs, 3) / (1.0 + z_src[k]) / (4.0 * pi);
+    }
+    return ok();
+}
 
 // ---- allocation-free whole step (static device scratch) ----------------------
 

@@ -123,6 +123,7 @@ struct FusedArgs {
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
     int32_t parity;          // 1: spectra in the parity y layout of the half-plane xy shapes
     int32_t ring = 0;        // lookback slice k is stored in spectrum slot (k + ring) mod K
+    int32_t frozen = -1;     // >= 0: every lookback slice reads spectrum slot `frozen`
     // band means mu[band0 + j] = inv_n3 * sum_k g0[k B + band0 + j] sk[k] (the FP64
     // DC mode), reduced by the first workgroup when mu is non-null
     const double *sk = nullptr, *g0 = nullptr;
@@ -174,6 +175,8 @@ hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, cons
 // lookback index (s - ring) mod K; status starts as {0, INT32_MAX}.
 hipError_t launch_dc_reduce(const double *dcpart, int K, int W, double *sk, int *status, int ring, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t st);
+// out = (j_inst - j) / j elementwise (0 where j == 0), FP64 arithmetic
+hipError_t launch_fdiff(const void *j, const void *j_inst, void *out, int64_t count, bool f64, hipStream_t st);
 // The same sums and check for the plain forms, read from the DC bin of each
 // slot's fully transformed spectrum (spec + s*stride, complex FP64 or FP32):
 // a NaN or infinity anywhere in a slice's sources reaches that bin.
