@@ -132,6 +132,11 @@ typedef struct {
  *   kind 1: point list, n entries: cell[i] in [0, N^3) (flat index, int64),
  *           lum[i] of type `dtype`. A device point list is deposited with
  *           FP64 atomics (summation order of coincident sources varies).
+ *   kind 2: positioned point list, n entries: `grid` points to 3n FP64
+ *           positions (i, j, k axis order, k contiguous, in length units,
+ *           any real values: wrapped periodically), lum[i] of type `dtype`;
+ *           deposited to the nearest node, round(x / l) mod N. The same
+ *           list feeds the near-field correction (lc_near_field).
  * `dtype` gives the value type of grid / lum, `mem` where they live. */
 typedef struct {
     int32_t kind;
@@ -224,6 +229,25 @@ int lc_step(lc_plan_t *plan, const lc_sources *srcs, void *const *out, int32_t d
  * LC_EINVAL if slice is outside [0, K) of a selected box. */
 int lc_field_frozen(lc_plan_t *plan, int32_t box, int32_t band, int32_t slice, void *const *out,
                     int32_t dtype, int32_t mem);
+
+/* Near-field (particle-mesh) correction of one band's field for sources
+ * with positions inside their cells (Sec. 4: direct summation for nearby
+ * sources, the FFT method for the far field). srcs holds the K slices'
+ * positioned point lists (kind 2, device memory, lookback order; n = 0 for
+ * none) that were pushed for the field in `out` (device, N^3 values of
+ * `dtype`, as written by lc_field / lc_step for this box and band). For
+ * every source s of slice k, nearest node c_s, and every node x = c_s + o
+ * with 0 < max|o_d| <= near_cells, the mesh kernel's primary-image value
+ * G_k(o) is replaced by the retarded kernel at the exact distance:
+ *   out[x] += L_s (F_k(|x l - x_s|) - G^prim_k(o)),
+ * F_k(r) = [r_k <= r < r_{k+1}] pref phi_k(r) / (4 pi r^2), and G^prim_k(o)
+ * the m^3-subpoint average of the image u = 0 with the same shell rule as
+ * the kernel. The source's own node keeps the cell-averaged mesh value.
+ * Requires (near_cells + 1) sqrt(3) l < L/2 (one image), near_cells in
+ * [1, 8]; corrections are summed with FP64 atomics (order varies).
+ * Errors: LC_EINVAL, LC_ESTATE (band not built), LC_EUNSUPPORTED. */
+int lc_near_field(lc_plan_t *plan, int32_t box, int32_t band, const lc_sources *srcs, int32_t near_cells,
+                  void *out, int32_t dtype);
 
 /* Fractional difference of two fields (Sec. 3, the comparison of the
  * instantaneous and the light-cone field): out[i] = (j_inst[i] - j[i]) / j[i]

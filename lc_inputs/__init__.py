@@ -225,6 +225,15 @@ def uneven_16boxes(seed_base: int = 5, sizes=(64, 96, 128, 192, 256), n_boxes: i
     return Workload(f"uneven{n_boxes}boxes", boxes)
 
 
+def positioned_sources(seed, L: float, count: int):
+    """Sources with continuous positions: uniform in [0, L)^3 (axis order
+    i, j, k), lognormal luminosities. Returns (pos (count, 3), lum)."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, L, size=(count, 3))
+    lum = rng.lognormal(mean=0.0, sigma=1.0, size=count)
+    return pos, lum
+
+
 def random_sources(seed, n: int, count: int):
     """Small generic case for tests: uniform cells, lognormal luminosity."""
     return uniform_sources(np.random.default_rng(seed), n ** 3, count)

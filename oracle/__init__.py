@@ -72,6 +72,8 @@ def lib():
         L.or_redshift_at_time.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_redshift_at_time.restype = C.c_double
         L.or_build_G_slices.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, ap, C.c_int, dp]
+        L.or_near_correction.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, ap, ip, dp, dp,
+                                         C.c_int, dp]
         L.or_dft3_brute.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
         L.or_conv3_brute.argtypes = [C.c_int, dp, dp, dp]
         L.or_num_threads.restype = C.c_int
@@ -200,6 +202,36 @@ def lw_factors(h: float, om: float, z_obs: float, z_src, kind: int = 2):
         alpha = (h / 0.7) ** -1 * (om / 0.27) ** -0.5 * ((1.0 + zs) / 21.0) ** -0.5
         out.append(_LWAtten(kind, 116.29 * alpha, 97.39 * alpha, (1.0 + z_obs) ** 3 / (1.0 + zs) / (4.0 * math.pi)))
     return out
+
+
+def ngp_cells(n: int, L: float, pos: np.ndarray) -> np.ndarray:
+    """Flat index of each positioned source's nearest node, round(x / l) mod N
+    per axis (axis order i, j, k; k contiguous)."""
+    l = L / n
+    c = np.mod(np.floor(np.asarray(pos, np.float64) / l + 0.5).astype(np.int64), n)
+    return (c[:, 0] * n + c[:, 1]) * n + c[:, 2]
+
+
+def near_correction(n: int, L: float, radii, m: int, attens, positioned, R: int) -> np.ndarray:
+    """Particle-mesh near-field correction (Sec. 4) of positioned sources:
+    positioned[k] = (pos (n_k, 3) in length units, lum (n_k,)); attens[k]
+    the radial factor of slice k. Returns the N^3 correction grid."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    K = len(radii) - 1
+    assert len(attens) == K and len(positioned) == K
+    off = np.zeros(K + 1, dtype=np.int64)
+    for k, (p, _) in enumerate(positioned):
+        off[k + 1] = off[k] + len(p)
+    pos = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1, 3) for p, _ in positioned])
+                               if off[-1] else np.zeros((0, 3)))
+    lum = np.ascontiguousarray(np.concatenate([np.asarray(v, np.float64) for _, v in positioned])
+                               if off[-1] else np.zeros(0))
+    arr = (_Atten * K)(*[_atten(a) for a in attens])
+    corr = np.zeros(n ** 3)
+    rc = lib().or_near_correction(n, L, K, _dptr(radii), m, arr, _iptr(off), _dptr(pos.ravel()), _dptr(lum),
+                                  int(R), _dptr(corr))
+    assert rc == 0
+    return corr.reshape(n, n, n)
 
 
 def frozen_sources(sources, slice_: int = 0):

@@ -586,6 +586,67 @@ int or_build_G_slices(int N, double L, int K, const double *radii, int m,
     return 0;
 }
 
+/* ---- near-field (particle-mesh) correction (Sec. 4) -------------------
+ * Sources with positions x_s inside their cells sit on their nearest node
+ * c_s = round(x_s / l) in the mesh field. For target nodes c_s + o with
+ * 0 < max|o_d| <= R the primary-image part of the mesh kernel, the
+ * m^3-subpoint average over the image u = 0 at displacement o, is replaced
+ * by the retarded kernel at the exact distance |(c_s + o) l - x_s|:
+ *   corr(c_s + o) += L (F_k(rho) - Gprim_k(o)).
+ * Slice k of the K point lists uses at[k]. Plain sequential FP64 sums. */
+static double or_G_primary(const kern_t *kp, int k, int o0, int o1, int o2)
+{
+    const int m = kp->m;
+    double acc = 0.0;
+    for (int a0 = 0; a0 < m; ++a0)
+    for (int a1 = 0; a1 < m; ++a1)
+    for (int a2 = 0; a2 < m; ++a2) {
+        int64_t q0 = 2 * m * (int64_t)o0 + (2 * a0 + 1 - m);
+        int64_t q1 = 2 * m * (int64_t)o1 + (2 * a1 + 1 - m);
+        int64_t q2 = 2 * m * (int64_t)o2 + (2 * a2 + 1 - m);
+        int64_t n = q0 * q0 + q1 * q1 + q2 * q2;
+        double dn = (double)n;
+        if (dn >= kp->T[k] && dn < kp->T[k + 1]) acc += point_value(kp, n);
+    }
+    return acc;
+}
+
+int or_near_correction(int N, double L, int K, const double *radii, int m, const or_atten *at,
+                       const int64_t *off, const double *pos, const double *lum, int R, double *corr)
+{
+    const double l = L / N;
+    memset(corr, 0, sizeof(double) * (int64_t)N * N * N);
+    for (int k = 0; k < K; ++k) {
+        kern_t kp;
+        if (kern_init(&kp, N, L, K, radii, m, &at[k])) return -1;
+        for (int64_t s = off[k]; s < off[k + 1]; ++s) {
+            double c[3];
+            for (int d = 0; d < 3; ++d) c[d] = floor(pos[3 * s + d] / l + 0.5);
+            for (int o0 = -R; o0 <= R; ++o0)
+            for (int o1 = -R; o1 <= R; ++o1)
+            for (int o2 = -R; o2 <= R; ++o2) {
+                if (o0 == 0 && o1 == 0 && o2 == 0) continue;
+                int o[3] = { o0, o1, o2 };
+                double r2 = 0.0;
+                int64_t cell = 0;
+                for (int d = 0; d < 3; ++d) {
+                    double y = (c[d] + o[d]) * l - pos[3 * s + d];
+                    r2 += y * y;
+                    int64_t v = ((int64_t)c[d] + o[d]) % N;
+                    if (v < 0) v += N;
+                    cell = cell * N + v;
+                }
+                double rho = sqrt(r2);
+                double F = 0.0;
+                if (rho >= radii[k] && rho < radii[k + 1])
+                    F = at[k].prefactor * or_phi(&at[k], rho) / (4.0 * OR_PI * rho * rho);
+                corr[cell] += lum[s] * (F - or_G_primary(&kp, k, o0, o1, o2));
+            }
+        }
+    }
+    return 0;
+}
+
 /* ---- naive DFT (Eq. 12 convention) ------------------------------------- */
 
 /* Twiddle table e^{sign 2 pi i j / N}, j in [0, N), from long double libm. */

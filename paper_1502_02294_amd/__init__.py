@@ -32,7 +32,7 @@ EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources
             "lc_field", "lc_step", "lc_check_sources", "lc_destroy", "lc_last_error",
             "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel", "lc_get_schedule",
             "lc_set_schedule", "lc_step_static", "lc_field_frozen", "lc_fdiff", "lc_cosmo_slices",
-            "lc_lw_factors", "lc_build_greens_slices"]
+            "lc_lw_factors", "lc_build_greens_slices", "lc_near_field"]
 
 (LC_KERNEL_X_FWD, LC_KERNEL_COL_Y_FWD, LC_KERNEL_COL_Z_FWD, LC_KERNEL_FUSED_Z, LC_KERNEL_MAC,
  LC_KERNEL_COL_Z_INV, LC_KERNEL_COL_Y_INV, LC_KERNEL_X_INV, LC_KERNEL_XY_FWD, LC_KERNEL_YX_INV) = range(10)
@@ -72,6 +72,16 @@ class lc_sources(C.Structure):
                 ("cell", C.c_void_p), ("lum", C.c_void_p)]
 
 
+class Positioned:
+    """Sources with positions inside their cells (lc_sources kind 2): pos an
+    (n, 3) float64 tensor in length units (axis order i, j, k), lum (n,)
+    float32/float64. Deposited to the nearest node; the same list feeds
+    Plan.near_field."""
+
+    def __init__(self, pos, lum):
+        self.pos, self.lum = pos, lum
+
+
 class LCError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -109,6 +119,8 @@ def load():
     L.lc_cosmo_slices.argtypes = [C.POINTER(lc_cosmo), C.c_double, C.c_double, C.c_int32, dp, dp, dp]
     L.lc_lw_factors.argtypes = [C.POINTER(lc_cosmo), C.c_double, C.c_int32, dp, C.c_int32, C.POINTER(lc_atten)]
     L.lc_build_greens_slices.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_atten)]
+    L.lc_near_field.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(lc_sources), C.c_int32, C.c_void_p,
+                                C.c_int32]
     L.lc_destroy.argtypes = [C.c_void_p]
     L.lc_destroy.restype = None
     L.lc_last_error.restype = C.c_char_p
@@ -120,7 +132,7 @@ def load():
     for name in ["lc_plan", "lc_build_greens", "lc_push_sources", "lc_advance", "lc_field", "lc_step",
                  "lc_check_sources", "lc_greens_imag_ratio", "lc_greens_dc", "lc_time_kernel",
                  "lc_get_schedule", "lc_set_schedule", "lc_step_static", "lc_field_frozen", "lc_fdiff",
-                 "lc_cosmo_slices", "lc_lw_factors", "lc_build_greens_slices"]:
+                 "lc_cosmo_slices", "lc_lw_factors", "lc_build_greens_slices", "lc_near_field"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -419,7 +431,24 @@ class Plan:
                          v.data_ptr() if v.numel() else None)
         return src, (c, v)
 
+    def _positioned_source(self, box: int, s, allow_host: bool, what: str):
+        torch = self.torch
+        self._box_n(box)
+        v = check_tensor(s.lum, what + " luminosities", dtypes=(torch.float32, torch.float64),
+                         device=self.device, allow_host=allow_host)
+        p = check_tensor(s.pos, what + " positions", dtypes=(torch.float64,), numel=3 * v.numel(),
+                         device=self.device, allow_host=allow_host)
+        if p.device != v.device:
+            raise ValueError(f"{what}: positions on {p.device} but luminosities on {v.device}")
+        dt = LC_F64 if v.dtype == torch.float64 else LC_F32
+        mem = LC_MEM_DEVICE if p.is_cuda else LC_MEM_HOST
+        src = lc_sources(2, dt, mem, 0, p.data_ptr() if v.numel() else None, int(v.numel()), None,
+                         v.data_ptr() if v.numel() else None)
+        return src, (p, v)
+
     def _source(self, box: int, s, allow_host: bool, what: str):
+        if isinstance(s, Positioned):
+            return self._positioned_source(box, s, allow_host, what)
         if isinstance(s, (tuple, list)):
             if len(s) != 2:
                 raise ValueError(f"{what}: a point list is a (cells, lum) pair")
@@ -438,6 +467,35 @@ class Plan:
         tensors on one device, the plan's or the host)."""
         src, keep = self._point_source(box, cells, lum, True, "point list")
         self._call(lc_push_sources, self.handle, box, slice_, src)
+        return keep
+
+    def push_positioned(self, box: int, slice_: int, pos, lum):
+        """Positioned sources (lc_sources kind 2): (n, 3) float64 positions in
+        length units and their luminosities, on the plan's device or the host."""
+        src, keep = self._positioned_source(box, Positioned(pos, lum), True, "positioned sources")
+        self._call(lc_push_sources, self.handle, box, slice_, src)
+        return keep
+
+    def near_field(self, box: int, band: int, positioned, near_cells: int, out):
+        """Add the particle-mesh near-field correction (lc_near_field) of the
+        K slices' positioned sources (a list of Positioned, lookback order) to
+        the field `out` (device tensor of this box and band)."""
+        torch = self.torch
+        n = self._box_n(box)
+        K = len(self.boxes[box].radii) - 1
+        if len(positioned) != K:
+            raise ValueError(f"near_field takes {K} positioned source lists, got {len(positioned)}")
+        srcs, keep = [], []
+        for k, s in enumerate(positioned):
+            src, kp = self._positioned_source(box, s, False, f"slice {k} positioned sources")
+            srcs.append(src)
+            keep.append(kp)
+        out = check_tensor(out, "field", dtypes=(torch.float32, torch.float64), numel=n ** 3, device=self.device,
+                           copy_ok=False)
+        arr = (lc_sources * K)(*srcs)
+        dt = LC_F64 if out.dtype == torch.float64 else LC_F32
+        self._call(lambda: _check(load().lc_near_field(self.handle, box, band, arr, int(near_cells),
+                                                       C.c_void_p(out.data_ptr()), dt)))
         return keep
 
     def advance(self, box: int, sources):

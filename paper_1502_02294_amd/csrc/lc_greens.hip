@@ -157,6 +157,163 @@ hipError_t launch_greens_fold(int n, const void *spec64, void *oct, bool oct_f64
 }
 
 // ---------------------------------------------------------------------------
+// near-field (particle-mesh) correction
+//
+// A source with a position inside its cell (x_s, in length units) is
+// deposited to its nearest node c_s = round(x_s / l) mod N. For target nodes
+// x = c_s + o, 0 < |o|_inf <= R, its mesh contribution L G_k(o) has a
+// primary-image part that the correction replaces by the retarded kernel at
+// the exact distance: J(x) += L (F_k(|x l - x_s|) - G^prim_k(o)), with
+// F_k(rho) = [r_k <= rho < r_{k+1}] pref phi(rho) / (4 pi rho^2) and
+// G^prim_k(o) the m^3-subpoint average of the image u = 0 (the same rule as
+// the builder). The source's own node keeps the mesh value. Distances are
+// formed without fused multiply-adds so that shell membership is decided
+// on the same rounded values as a plain FP64 evaluation.
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+// index in [0, n) of node coordinate c (a whole number), wrapped periodically
+__device__ __forceinline__ int64_t wrap_node(double c, int n) {
+    double v = fmod(c, (double)n);
+    if (v < 0.0) v += (double)n;
+    if (v >= (double)n) v -= (double)n;
+    return (int64_t)v;
+}
+
+__global__ __launch_bounds__(256) void near_table_kernel(NearArgs a) {
+    const int R = a.R, W = R + 1;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)W * W * W) return;
+    const int d0 = (int)(e / (W * W)), d1 = (int)((e / W) % W), d2 = (int)(e % W);
+    const int m = a.m;
+    const double four_pi = 12.566370614359172954;
+    const double wm = a.pref / ((double)m * m * m);
+    double acc = 0.0;
+    if (d0 | d1 | d2) {
+        for (int a0 = 0; a0 < m; ++a0) {
+            const int64_t q0 = 2 * m * (int64_t)d0 + (2 * a0 + 1 - m);
+            for (int a1 = 0; a1 < m; ++a1) {
+                const int64_t q1 = 2 * m * (int64_t)d1 + (2 * a1 + 1 - m);
+                for (int a2 = 0; a2 < m; ++a2) {
+                    const int64_t q2 = 2 * m * (int64_t)d2 + (2 * a2 + 1 - m);
+                    const double dn = (double)(q0 * q0 + q1 * q1 + q2 * q2);
+                    if (dn >= a.t_lo && dn < a.t_hi) {
+                        const double rho = sqrt(dn) * a.h;
+                        acc += wm * phi_eval(a.kind, rho, a.a, a.s, a.p, a.c, a.cut) / (four_pi * rho * rho);
+                    }
+                }
+            }
+        }
+    }
+    a.table[e] = acc;
+}
+
+template <typename TL>
+__global__ __launch_bounds__(256) void near_corr_kernel(NearArgs a, int64_t n_pts, const double *__restrict__ pos,
+                                                        const TL *__restrict__ lum) {
+    const int R = a.R, D = 2 * R + 1, W = R + 1;
+    const int64_t V = (int64_t)D * D * D;
+    const int n = a.n;
+    const double four_pi = 12.566370614359172954;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_pts * V;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = e / V;
+        const int o = (int)(e % V);
+        const int o0 = o / (D * D) - R, o1 = (o / D) % D - R, o2 = o % D - R;
+        if (!(o0 | o1 | o2)) continue;
+        const double p0 = pos[3 * s], p1 = pos[3 * s + 1], p2 = pos[3 * s + 2];
+        // a non-finite position has no cell (its slice is flagged by the deposit)
+        if (!isfinite(p0) || !isfinite(p1) || !isfinite(p2)) continue;
+        const double L = (double)lum[s];
+        const double c0 = floor(p0 / a.l + 0.5), c1 = floor(p1 / a.l + 0.5), c2 = floor(p2 / a.l + 0.5);
+        const double y0 = (c0 + o0) * a.l - p0, y1 = (c1 + o1) * a.l - p1, y2 = (c2 + o2) * a.l - p2;
+        const double rho = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
+        double F = 0.0;
+        if (rho >= a.r_lo && rho < a.r_hi)
+            F = a.pref * phi_eval(a.kind, rho, a.a, a.s, a.p, a.c, a.cut) / (four_pi * rho * rho);
+        const int t0 = o0 < 0 ? -o0 : o0, t1 = o1 < 0 ? -o1 : o1, t2 = o2 < 0 ? -o2 : o2;
+        const double M = a.table[((int64_t)t0 * W + t1) * W + t2];
+        const double dv = L * (F - M);
+        if (dv == 0.0) continue;
+        const int64_t cell =
+            (wrap_node(c0 + o0, n) * n + wrap_node(c1 + o1, n)) * n + wrap_node(c2 + o2, n);
+        atomicAdd(&a.corr[cell], dv);
+    }
+}
+
+// nearest-node deposit of positioned sources (positions in length units,
+// wrapped periodically)
+template <typename TL>
+__global__ __launch_bounds__(256) void deposit_pos_kernel(double *__restrict__ grid, int64_t n_pts,
+                                                          const double *__restrict__ pos,
+                                                          const TL *__restrict__ lum, int n, double l) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_pts;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double p0 = pos[3 * e], p1 = pos[3 * e + 1], p2 = pos[3 * e + 2];
+        if (!isfinite(p0) || !isfinite(p1) || !isfinite(p2)) {
+            // no cell: make the slice's sum non-finite so that the check flags it
+            atomicAdd(&grid[0], (double)NAN);
+            continue;
+        }
+        const int64_t cell = (wrap_node(floor(p0 / l + 0.5), n) * n + wrap_node(floor(p1 / l + 0.5), n)) * n +
+                             wrap_node(floor(p2 / l + 0.5), n);
+        atomicAdd(&grid[cell], (double)lum[e]);
+    }
+}
+#pragma clang fp contract(on)
+
+template <typename TO>
+__global__ __launch_bounds__(256) void add_grid_kernel(TO *__restrict__ out, const double *__restrict__ corr,
+                                                       int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        if (corr[e] != 0.0) out[e] = (TO)((double)out[e] + corr[e]);
+}
+
+hipError_t launch_near_table(const NearArgs &a, hipStream_t st) {
+    const int64_t cells = (int64_t)(a.R + 1) * (a.R + 1) * (a.R + 1);
+    hipLaunchKernelGGL(near_table_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_corr(const NearArgs &a, int64_t n_pts, const double *pos, const void *lum, bool lum_f64,
+                            hipStream_t st) {
+    if (n_pts <= 0) return hipSuccess;
+    const int64_t D = 2 * a.R + 1;
+    const int64_t work = n_pts * D * D * D;
+    const int wgs = (int)std::min<int64_t>((work + 255) / 256, 16384);
+    if (lum_f64)
+        hipLaunchKernelGGL(near_corr_kernel<double>, dim3(wgs), dim3(256), 0, st, a, n_pts, pos,
+                           (const double *)lum);
+    else
+        hipLaunchKernelGGL(near_corr_kernel<float>, dim3(wgs), dim3(256), 0, st, a, n_pts, pos,
+                           (const float *)lum);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_pos(double *grid, int64_t n_pts, const double *pos, const void *lum, bool lum_f64, int n,
+                              double l, hipStream_t st) {
+    if (n_pts <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((n_pts + 255) / 256, 8192);
+    if (lum_f64)
+        hipLaunchKernelGGL(deposit_pos_kernel<double>, dim3(wgs), dim3(256), 0, st, grid, n_pts, pos,
+                           (const double *)lum, n, l);
+    else
+        hipLaunchKernelGGL(deposit_pos_kernel<float>, dim3(wgs), dim3(256), 0, st, grid, n_pts, pos,
+                           (const float *)lum, n, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_grid(void *out, bool out_f64, const double *corr, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int wgs = (int)std::min<int64_t>((count + 255) / 256, 16384);
+    if (out_f64)
+        hipLaunchKernelGGL(add_grid_kernel<double>, dim3(wgs), dim3(256), 0, st, (double *)out, corr, count);
+    else
+        hipLaunchKernelGGL(add_grid_kernel<float>, dim3(wgs), dim3(256), 0, st, (float *)out, corr, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // utilities
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fill_f64_kernel(double *__restrict__ p, int64_t count, double v) {

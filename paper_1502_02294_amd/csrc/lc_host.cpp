@@ -225,6 +225,7 @@ struct BoxPlan {
     double L = 0, l = 0, h = 0;
     std::vector<double> radii, T;
     std::vector<int> built, kcount;
+    std::vector<std::vector<Atten>> att;   // per band, per slice: the radial factors of the last build
     std::vector<uint8_t> pushed;          // per slot
     // dense device sources of the most recent push of each slot (diagnostic timing)
     std::vector<const void *> last_src;
@@ -419,6 +420,14 @@ int valid_sources(const BoxPlan &bp, const lc_sources *s) {
                 if (s->cell[i] < 0 || s->cell[i] >= n3)
                     return fail(LC_EINVAL, "point %lld: cell %lld outside [0, N^3)", (long long)i,
                                 (long long)s->cell[i]);
+        }
+    } else if (s->kind == 2) {
+        if (s->n < 0) return fail(LC_EINVAL, "point count must be >= 0");
+        if (s->n > 0 && (!s->grid || !s->lum)) return fail(LC_EINVAL, "positioned point list pointers are NULL");
+        if (s->mem == LC_MEM_HOST) {
+            const double *pos = (const double *)s->grid;
+            for (int64_t i = 0; i < 3 * s->n; ++i)
+                if (!std::isfinite(pos[i])) return fail(LC_EINVAL, "point %lld: position not finite", (long long)(i / 3));
         }
     } else {
         return fail(LC_EINVAL, "unknown source kind %d", s->kind);
@@ -633,6 +642,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             bp.T[k] = q * q;
         }
         bp.built.assign(bp.B, 0);
+        bp.att.assign(bp.B, std::vector<Atten>());
         bp.kcount.assign(bp.B, bp.K);
         bp.pushed.assign(bp.K, 0);
         bp.last_src.assign(bp.K, nullptr);
@@ -803,6 +813,7 @@ int build_impl(lc_plan_t *p, BoxPlan &bp, int band, const std::vector<Atten> &A)
     }
     bp.kcount[band] = kc;
     bp.built[band] = 1;
+    bp.att[band] = A;
     // a captured step holds this band's slice count (launch shapes of the
     // slice sum): the next lc_step captures again
     p->gkey.clear();
@@ -862,6 +873,31 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
             HIPCHK(hipStreamSynchronize(st));
             in = p->scratch_real;
         }
+    } else if (s->kind == 2) {
+        // positioned sources: nearest-node deposit
+        in_f64 = true;
+        if (s->mem == LC_MEM_DEVICE) {
+            HIPCHK(launch_fill_f64((double *)p->scratch_real, n3, 0.0, st));
+            HIPCHK(launch_deposit_pos((double *)p->scratch_real, s->n, (const double *)s->grid, s->lum,
+                                      s->dtype == LC_F64, n, bp.l, st));
+        } else {
+            std::vector<double> g((size_t)n3, 0.0);
+            const double *pos = (const double *)s->grid;
+            for (int64_t i = 0; i < s->n; ++i) {
+                int64_t c[3];
+                for (int d = 0; d < 3; ++d) {
+                    double v = std::fmod(std::floor(pos[3 * i + d] / bp.l + 0.5), (double)n);
+                    if (v < 0.0) v += n;
+                    if (v >= n) v -= n;
+                    c[d] = (int64_t)v;
+                }
+                g[(size_t)((c[0] * n + c[1]) * n + c[2])] += s->dtype == LC_F64 ? ((const double *)s->lum)[i]
+                                                                               : (double)((const float *)s->lum)[i];
+            }
+            HIPCHK(hipMemcpyAsync(p->scratch_real, g.data(), (size_t)n3 * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        in = p->scratch_real;
     } else {
         in_f64 = true;
         if (s->mem == LC_MEM_DEVICE) {
@@ -1082,6 +1118,50 @@ int lc_fdiff(const void *j, const void *j_inst, void *out, int64_t count, int32_
     if (count > 0 && (!j || !j_inst || !out)) return fail(LC_EINVAL, "NULL field pointer");
     if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad dtype");
     HIPCHK(launch_fdiff(j, j_inst, out, count, dtype == LC_F64, (hipStream_t)hip_stream));
+    return ok();
+}
+
+int lc_near_field(lc_plan_t *p, int32_t box, int32_t band, const lc_sources *srcs, int32_t near_cells, void *out,
+                  int32_t dtype) {
+    if (!p) return fail(LC_EINVAL, "plan is NULL");
+    if (box < 0 || box >= (int)p->boxes.size()) return fail(LC_EINVAL, "box %d out of range", box);
+    BoxPlan &bp = p->boxes[box];
+    if (band < 0 || band >= bp.B) return fail(LC_EINVAL, "band %d out of range", band);
+    if (!bp.built[band]) return fail(LC_ESTATE, "kernel of box %d band %d not built", box, band);
+    if (!srcs || !out) return fail(LC_EINVAL, "srcs/out is NULL");
+    if (dtype != LC_F32 && dtype != LC_F64) return fail(LC_EINVAL, "bad output dtype");
+    const int R = near_cells;
+    if (R < 1 || R > 8) return fail(LC_EINVAL, "near_cells must be in [1, 8]");
+    // one periodic image: the farthest corrected node lies below half the box
+    if (!((R + 1) * std::sqrt(3.0) * bp.l < 0.5 * bp.L))
+        return fail(LC_EUNSUPPORTED, "near_cells = %d reaches beyond half the box (N = %d)", R, bp.n);
+    for (int k = 0; k < bp.K; ++k) {
+        const lc_sources &s = srcs[k];
+        if (s.kind != 2) return fail(LC_EINVAL, "slice %d: near-field sources must be positioned (kind 2)", k);
+        int rc = valid_sources(bp, &s);
+        if (rc) return rc;
+        if (s.mem != LC_MEM_DEVICE) return fail(LC_EINVAL, "slice %d: near-field sources must be in device memory", k);
+    }
+    const int n = bp.n;
+    const int64_t n3 = (int64_t)n * n * n;
+    hipStream_t st = p->stream;
+    double *corr = (double *)p->scratch_real;
+    HIPCHK(launch_fill_f64(corr, n3, 0.0, st));
+    NearArgs a;
+    a.n = n; a.m = bp.m; a.R = R; a.l = bp.l; a.h = bp.h;
+    a.table = (double *)p->scratch_spec;
+    a.corr = corr;
+    for (int k = 0; k < bp.K; ++k) {
+        const lc_sources &s = srcs[k];
+        const Atten &A = bp.att[band][k];
+        if (s.n == 0 || k >= bp.kcount[band] || A.pref == 0.0) continue;
+        a.t_lo = bp.T[k]; a.t_hi = bp.T[k + 1];
+        a.r_lo = bp.radii[k]; a.r_hi = bp.radii[k + 1];
+        a.kind = A.kind; a.a = A.a; a.s = A.s; a.p = A.p; a.c = A.c; a.cut = A.cut; a.pref = A.pref;
+        HIPCHK(launch_near_table(a, st));
+        HIPCHK(launch_near_corr(a, s.n, (const double *)s.grid, s.lum, s.dtype == LC_F64, st));
+    }
+    HIPCHK(launch_add_grid(out, dtype == LC_F64, corr, n3, st));
     return ok();
 }
 

@@ -165,6 +165,25 @@ hipError_t launch_greens_fold(int n, const void *spec64, void *oct, bool oct_f64
                               double target_over_l3, double *dc, unsigned long long *maxima,
                               hipStream_t st);
 
+// Near-field (particle-mesh) correction of one slice: its shell, thresholds
+// and radial factor.
+struct NearArgs {
+    int32_t n, m, R;           // grid side, subpoints per axis, near radius in cells
+    double l, h;
+    double t_lo, t_hi;         // T_k, T_{k+1}
+    double r_lo, r_hi;         // r_k, r_{k+1}
+    int32_t kind;
+    double a, s, p, c, cut, pref;
+    double *table;             // (R+1)^3 primary-image mesh kernel of the slice (device)
+    double *corr;              // N^3 FP64 correction accumulator (device)
+};
+hipError_t launch_near_table(const NearArgs &a, hipStream_t st);
+hipError_t launch_near_corr(const NearArgs &a, int64_t n_pts, const double *pos, const void *lum, bool lum_f64,
+                            hipStream_t st);
+hipError_t launch_deposit_pos(double *grid, int64_t n_pts, const double *pos, const void *lum, bool lum_f64, int n,
+                              double l, hipStream_t st);
+hipError_t launch_add_grid(void *out, bool out_f64, const double *corr, int64_t count, hipStream_t st);
+
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_bytes(void *p, int64_t bytes, hipStream_t st);   // zero, bytes % 4 == 0
 hipError_t launch_deposit(double *grid, int64_t n_pts, const int64_t *cell, const void *lum,
