@@ -17,8 +17,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lc.h"
@@ -525,7 +528,43 @@ hipError_t tune_forward(lc_plan_t *p, BoxPlan &bp, int xyv, int cnt, int k0) {
 // within timing noise of each other do not change the choice from one plan
 // to the next.
 constexpr double kTuneMargin = 0.98;
+
+// Shapes chosen by autotune_box, kept for the life of the process and reused
+// by later plans with the same device, grid side, slice count and bands per
+// fused launch (the trial launches take ~0.1-1 s per plan).
+struct TunedShape {
+    int xy_variant, push_group, fused_variant, fused_rounds;
+};
+using TuneKey = std::tuple<int, int, int, int>;   // device, N, K, bands per fused launch
+std::mutex g_tune_mu;
+std::map<TuneKey, TunedShape> g_tuned;
+
+int autotune_box_uncached(lc_plan_t *p, BoxPlan &bp);
+
 int autotune_box(lc_plan_t *p, BoxPlan &bp) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const TuneKey key{dev, bp.n, bp.K, std::min(2, bp.B)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            bp.xy_variant = it->second.xy_variant;
+            bp.push_group = it->second.push_group;
+            bp.fused_variant = it->second.fused_variant;
+            bp.fused_rounds = it->second.fused_rounds;
+            bp.dcw = bp.dc_width();
+            return LC_OK;
+        }
+    }
+    int rc = autotune_box_uncached(p, bp);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = TunedShape{bp.xy_variant, bp.push_group, bp.fused_variant, bp.fused_rounds};
+    return LC_OK;
+}
+
+int autotune_box_uncached(lc_plan_t *p, BoxPlan &bp) {
     const int n = bp.n;
     const int reps = 3;
     double ms = 0.0;
