@@ -192,6 +192,7 @@ template <int L> struct Sched8;
     };
 LC_SCHED8(64, 2, 8, 8, 0, 0, 8)
 LC_SCHED8(128, 3, 8, 2, 8, 0, 16)
+LC_SCHED8(192, 3, 8, 3, 8, 0, 24)
 LC_SCHED8(256, 3, 8, 4, 8, 0, 32)
 LC_SCHED8(384, 4, 8, 3, 4, 4, 48)
 LC_SCHED8(512, 3, 8, 8, 8, 0, 64)

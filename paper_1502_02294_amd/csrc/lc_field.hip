@@ -626,7 +626,7 @@ static void fused_sets(ColSet &s0, ColSet &s1, bool pair = false) {
 
 // variant 1: eight elements per thread (Sched8), where a schedule exists
 template <int N> struct HasSched8 {
-    static constexpr bool value = (N == 64 || N == 128 || N == 256 || N == 384 || N == 512);
+    static constexpr bool value = (N == 64 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512);
 };
 
 template <int N, int NB, typename S, int PF, bool PAR>
@@ -693,8 +693,9 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
 
 // parity-layout input: compiled where a half-plane xy shape exists (the
 // pair tiles need rows that split into whole tiles)
-template <int N> constexpr bool fused_par() { return N == 256; }
+template <int N> constexpr bool fused_par() { return N == 192 || N == 256; }
 static_assert((256 / 2) % FusedShape<256, FusedTiling<256>>::CPW == 0, "pair tiles cover whole rows");
+static_assert((192 / 2) % FusedShape<192, FusedTiling<192>>::CPW == 0, "pair tiles cover whole rows");
 
 template <int N, bool PAR>
 static hipError_t fused_sched(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
@@ -749,9 +750,11 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
 // registers: the two-band instances need it), bit 1 the eight-element
 // schedule where one exists (N = 384, 512: the eight-element schedule only,
 // bit 0 alone)
-int fused_variants(int n) { return (n == 384 || n == 512) ? 2 : (n == 64 || n == 128 || n == 256) ? 4 : 2; }
+int fused_variants(int n) {
+    return (n == 384 || n == 512) ? 2 : (n == 64 || n == 128 || n == 192 || n == 256) ? 4 : 2;
+}
 
-bool fused_parity_supported(int n) { return n == 256; }
+bool fused_parity_supported(int n) { return n == 192 || n == 256; }
 
 // Built-in choice: prefetch depth 2 for one band per launch, 1 for two (the
 // two-band instances of depth 2 spill registers).

@@ -228,7 +228,12 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, NC_, NR_>::NT)) void xy_fwd_ke
             for (int e = 0; e < EXN; ++e) {
                 const cx<float> sv = xr[b][partner_e<RL, BPTL>(e, false)];
                 const cx<float> o = mk(partner_val<TX>(sv.x), partner_val<TX>(sv.y));
-                pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
+                // (component-wise selects of values: a select between two
+                // cx lvalues becomes a pointer select, which keeps the whole
+                // row array in scratch memory where the partner index is
+                // not a power of two)
+                const cx<float> own = xr[b][partner_e<RL, BPTL>(e, true)];
+                pv[e] = mk(t0 ? own.x : o.x, t0 ? own.y : o.y);
             }
 #pragma unroll
             for (int e = 0; e < EXN; ++e) {
@@ -473,13 +478,12 @@ __global__ __launch_bounds__((XYShape<N, S8, NB_, 0, N / 2>::NT)) void yx_inv_ke
     });
 }
 
-bool yx_inv_supported(int n) { return n == 256; }
+bool yx_inv_supported(int n) { return n == 192 || n == 256; }
 
-hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const void *tw_half, const void *twist,
-                         const void *tw_full, double scale, const double *mu, const int *split_tab,
-                         const void *part, hipStream_t st) {
-    if (n != 256 || !mu) return hipErrorInvalidValue;
-    constexpr int N = 256;
+template <int N>
+static hipError_t yx_inv_t(const void *acc, void *out, bool out_f64, const void *tw_half, const void *twist,
+                           const void *tw_full, double scale, const double *mu, const int *split_tab,
+                           const void *part, hipStream_t st) {
     constexpr bool S8 = false;
     constexpr int NB = 4;
     using SH = XYShape<N, S8, NB, 0, N / 2>;
@@ -497,6 +501,15 @@ hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const 
     }
 #undef YI_
     return hipGetLastError();
+}
+
+hipError_t launch_yx_inv(int n, const void *acc, void *out, bool out_f64, const void *tw_half, const void *twist,
+                         const void *tw_full, double scale, const double *mu, const int *split_tab,
+                         const void *part, hipStream_t st) {
+    if (!mu) return hipErrorInvalidValue;
+    if (n == 256) return yx_inv_t<256>(acc, out, out_f64, tw_half, twist, tw_full, scale, mu, split_tab, part, st);
+    if (n == 192) return yx_inv_t<192>(acc, out, out_f64, tw_half, twist, tw_full, scale, mu, split_tab, part, st);
+    return hipErrorInvalidValue;
 }
 
 // Forward x pass alone, FP32 spectrum, for N = 512 (a z-plane is too large
@@ -589,7 +602,8 @@ __global__ __launch_bounds__(XRowShape<N>::NT) void x_rows_kernel(SrcTab srcs, c
         for (int e = 0; e < EXN; ++e) {
             const cx<float> sv = xr[b][partner_e<RL, BPTL>(e, false)];
             const cx<float> o = mk(partner_val<TX>(sv.x), partner_val<TX>(sv.y));
-            pv[e] = t0 ? xr[b][partner_e<RL, BPTL>(e, true)] : o;
+            const cx<float> own = xr[b][partner_e<RL, BPTL>(e, true)];
+            pv[e] = mk(t0 ? own.x : o.x, t0 ? own.y : o.y);
         }
         const int64_t row = row0 + b * RPB + xl;
 #pragma unroll
@@ -644,11 +658,16 @@ hipError_t launch_x_rows_batch(int n, const SrcTab &in, int count, bool in_f64, 
 bool xy_supported(int n) { return n == 64 || n == 96 || n == 128 || n == 192 || n == 256; }
 
 // Launch shapes compiled per N (schedule, batches); the plan picks one.
-// At N = 256, shapes 4..6 take the rows of one parity per workgroup (half a
-// plane: two workgroups fit on a CU) and leave the spectrum in the parity
-// layout that the fused z pass completes.
-int xy_variants(int n) { return n == 256 ? 7 : (n == 128 || n == 192) ? 2 : xy_supported(n) ? 1 : 0; }
-bool xy_parity(int n, int variant) { return n == 256 && variant >= 4 && variant < 7; }
+// At N = 256 shapes 4..6, at N = 192 shapes 2..3, take the rows of one
+// parity per workgroup (half a plane: two or more workgroups fit on a CU)
+// and leave the spectrum in the parity layout that the fused z pass
+// completes.
+int xy_variants(int n) { return n == 256 ? 7 : n == 192 ? 4 : n == 128 ? 2 : xy_supported(n) ? 1 : 0; }
+static int xy_first_parity(int n) { return n == 256 ? 4 : n == 192 ? 2 : -1; }
+bool xy_parity(int n, int variant) {
+    const int f = xy_first_parity(n);
+    return f >= 0 && variant >= f && variant < xy_variants(n);
+}
 
 template <int N, int NR, typename TIN, bool S8, int NB, int NC, bool PER>
 static hipError_t xy_t(const SrcTab &in, int count, void *spec, int64_t spec_stride, const void *tw_half,
@@ -686,7 +705,7 @@ hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, 
     if (variant < 0 || variant >= xy_variants(n)) return hipErrorInvalidValue;
     // FP64 input takes the first shape of the same spectrum layout (the
     // FP64-input instances of the other shapes spill)
-    if (in_f64) variant = xy_parity(n, variant) ? 4 : 0;
+    if (in_f64) variant = xy_parity(n, variant) ? xy_first_parity(n) : 0;
 #define XS_(N, NR, S8, NB, NC, PER)                                                                            \
     return in_f64 ? xy_t<N, NR, double, S8, NB, NC, false>(in, count, spec, spec_stride, tw_half, twist,       \
                                                            tw_full, dcpart, dc_stride, st)                        \
@@ -702,7 +721,9 @@ hipError_t launch_xy_fwd_batch(int n, const SrcTab &in, int count, bool in_f64, 
             X_(128, true, 2, 0, false)
         case 192:
             if (variant == 0) { X_(192, false, 4, 3, false) }
-            X_(192, false, 4, 0, false)
+            if (variant == 1) { X_(192, false, 4, 0, false) }
+            if (variant == 2) { XH_(192, false, 4, 1) }
+            XH_(192, false, 2, 1)
         case 256:
             if (variant == 0) { X_(256, true, 8, 3, false) }
             if (variant == 1) { X_(256, false, 4, 1, false) }

@@ -87,8 +87,13 @@ def test_every_xy_shape_against_oracle(n):
     plan.close()
 
 
+# first half-plane (parity layout) xy shape compiled at each N
+PARITY_FIRST = {192: 2, 256: 4}
+
+
+@pytest.mark.parametrize("n", [192, 256])
 @pytest.mark.parametrize("nbands", [1, 2])
-def test_parity_layout_every_fused_schedule(nbands):
+def test_parity_layout_every_fused_schedule(nbands, n):
     """The half-plane xy shapes leave the y transforms of the even and the odd
     rows apart (T[q] = E[q mod N/2] + W_N^q O[q mod N/2], Sec. 2.2's FFT
     route with the last radix-2 step of the y transform deferred); the fused
@@ -98,7 +103,7 @@ def test_parity_layout_every_fused_schedule(nbands):
     (split-tile parts added by the inverse pass), one and two bands per
     launch, FP32 and FP64 output, against the oracle on sampled cells."""
     lc = _lc()
-    n, K = 256, 3
+    K = 3
     box = _box(n, K=K, seed=31 + nbands)
     L = box.box
     if nbands == 2:
@@ -109,8 +114,8 @@ def test_parity_layout_every_fused_schedule(nbands):
     plan = lc.Plan([box], precision=lc.LC_PREC_FP32)
     plan.build_all()
     sch = plan.get_schedule(0)
-    par = [v for v in range(sch["n_xy"]) if v >= 4]
-    assert par, "N = 256 compiles half-plane xy shapes"
+    par = [v for v in range(sch["n_xy"]) if v >= PARITY_FIRST[n]]
+    assert par, f"N = {n} compiles half-plane xy shapes"
     for xv in par:
         plan.set_schedule(0, xy_variant=xv)
         keep = [plan.push_grid(0, k, torch.from_numpy(li.dense_grid(n, cells, lum, np.float32)).cuda())
@@ -119,7 +124,7 @@ def test_parity_layout_every_fused_schedule(nbands):
         del keep
         for fv in range(sch["n_fused"]):
             for r in (1, 0):
-                print(f"case parity nbands={nbands} xy={xv} fused={fv} rounds={r}", flush=True)
+                print(f"case parity n={n} nbands={nbands} xy={xv} fused={fv} rounds={r}", flush=True)
                 plan.set_schedule(0, xy_variant=xv, fused_variant=fv, fused_rounds=r)
                 for b in range(nbands):
                     # (FP64 output once: the fused inverse pass's FP64 epilogue)
