@@ -377,7 +377,14 @@ typedef enum {
  *                  between the workgroups; a tile's second part is merged by
  *                  the inverse y pass
  *   push_group     slices per batched forward launch in lc_step, 1..64
- *   n_xy, n_fused  (lc_get_schedule only) shapes compiled for this N/form
+ *   fused_bands    bands that one fused z launch takes (each launch reads
+ *                  the slice spectra once), 1..n_fused_bands (FP32 form; -1
+ *                  in the other forms). With 1 or 2 the sum over slices is
+ *                  compensated (Kahan); with 3 or 4 (N = 384, 512) it is a
+ *                  plain FP32 sum. Default n_fused_bands; not tuned.
+ *   n_xy, n_fused, n_fused_bands  (lc_get_schedule only) shapes compiled
+ *                  for this N/form; n_fused_bands = min(B, 4 at N = 384,
+ *                  512, else 2)
  * lc_set_schedule validates every field (LC_EINVAL) and applies them to
  * later launches; the next lc_step captures a new graph. Changing whether
  * the fused xy pass is used, or between whole-plane and parity-layout
@@ -391,6 +398,8 @@ typedef struct {
     int32_t push_group;
     int32_t n_xy;
     int32_t n_fused;
+    int32_t fused_bands;
+    int32_t n_fused_bands;
 } lc_schedule;
 
 int lc_get_schedule(lc_plan_t *plan, int32_t box, lc_schedule *out);
@@ -404,7 +413,7 @@ int lc_set_schedule(lc_plan_t *plan, int32_t box, const lc_schedule *s);
  * LC_KERNEL_XY_FWD runs in the step's configuration, min(push_group, K)
  * slices per launch (lc_schedule), and its time is per launch; per-band
  * kernels
- * use band 0 (the fused pass handles bands 0-1); the output of
+ * use band 0 (the fused pass handles bands 0 .. fused_bands-1); the output of
  * LC_KERNEL_X_INV goes to the workspace scratch. Kernels must be built.
  * The plan's spectra and accumulators are left unspecified: push every
  * slice again before the next lc_field. Synchronises the stream.

@@ -82,7 +82,8 @@ struct FusedDev {
     int64_t spec_stride;
     const float *ghat;
     int64_t oct_stride;
-    int32_t B, band0, K0, K1;   // kcount of the two handled bands
+    int32_t B, band0, nb;       // bands in the G^ layout, first handled band, handled bands
+    int32_t Kc[4];              // kcount of the handled bands (0 past nb)
     cx<float> *acc;
     int64_t acc_stride;
     cx<float> *part;            // [band][P][L * CPW]
@@ -152,6 +153,10 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     constexpr int RSTEP = NT / CPW;                        // = threads per column
     constexpr int GROWS = (HP + RSTEP - 1) / RSTEP;        // octant rows loaded per thread
     constexpr int NO = PAR ? 2 : 1;                        // output columns per input column
+    // compensated (Kahan) sums for one or two bands per launch; four bands
+    // per launch keep plain FP32 sums (their compensation terms would not
+    // fit in registers beside the sums)
+    constexpr bool CS = NB_ <= 2;
     // pair tiles of one band: the two outputs' transforms run interleaved
     // (Engine::first2_db / rest2_db), two barriers per slice instead of four
     constexpr bool IL = PAR && NB_ == 1 && EF::NP > 1;
@@ -174,6 +179,7 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
     if (a.mu && blockIdx.x == 0 && threadIdx.x < 64) {
 #pragma unroll
         for (int b = 0; b < NB_; ++b) {
+            if (b >= a.nb) break;
             double v = 0.0;
             for (int k = threadIdx.x; k < a.K; k += 64) {
                 const int slot = a.frozen >= 0 ? a.frozen : (k + a.ring < a.K ? k + a.ring : k + a.ring - a.K);
@@ -223,13 +229,16 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
             if constexpr (PAR) gdel = fold(q + H, L) - fold(q, L);
         }
 
-        cx<float> sum[NO][NB_][E], cmp[NO][NB_][E];
+        cx<float> sum[NO][NB_][E], cmp[NO][CS ? NB_ : 1][CS ? E : 1];
 #pragma unroll
         for (int o = 0; o < NO; ++o)
 #pragma unroll
             for (int b = 0; b < NB_; ++b)
 #pragma unroll
-                for (int e = 0; e < E; ++e) { sum[o][b][e] = mk(0.f, 0.f); cmp[o][b][e] = mk(0.f, 0.f); }
+                for (int e = 0; e < E; ++e) {
+                    sum[o][b][e] = mk(0.f, 0.f);
+                    if constexpr (CS) cmp[o][b][e] = mk(0.f, 0.f);
+                }
 
         // Byte offsets, off workgroup-uniform bases (a slice spectrum is below
         // 4 GiB): of this thread's first input element, the others being whole
@@ -293,11 +302,13 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         auto load_g = [&](int k) {
 #pragma unroll
             for (int b = 0; b < NB_; ++b) {
-                const int kc = b == 0 ? a.K0 : a.K1;
+                const int kc = a.Kc[b];
                 const bool on = k < kc && k < k1;
                 const int kb = on ? k : 0;
                 gw[b] = on ? 1.f : 0.f;
-                const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + b) * a.oct_stride);
+                // (a band past nb reads the first handled band's octant)
+                const int bb = b < a.nb ? b : 0;
+                const char *gp = (const char *)(a.ghat + ((int64_t)kb * a.B + a.band0 + bb) * a.oct_stride);
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
                     // the second output's rows are gdel floats away (gdel < 0
@@ -326,19 +337,23 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                         if (rf < HP) glk[(b * NO + o) * HP * CPW + rf * CPW + c] = gw[b] * gn[b][o][jj];
                     }
         };
-        // compensated (Kahan) sum over slices of output o
+        // compensated (Kahan) sum over slices of output o, or the plain sum
         auto mac = [&](int o, const float *glk, const cx<float>(&v)[E]) {
 #pragma unroll
             for (int b = 0; b < NB_; ++b)
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const float gv = glk[(b * NO + o) * HP * CPW + gslot[e]];
-                    const float yx = gv * v[e].x - cmp[o][b][e].x, yy = gv * v[e].y - cmp[o][b][e].y;
-                    const float tx = sum[o][b][e].x + yx, ty = sum[o][b][e].y + yy;
-                    cmp[o][b][e].x = (tx - sum[o][b][e].x) - yx;
-                    cmp[o][b][e].y = (ty - sum[o][b][e].y) - yy;
-                    sum[o][b][e].x = tx;
-                    sum[o][b][e].y = ty;
+                    if constexpr (CS) {
+                        const float yx = gv * v[e].x - cmp[o][b][e].x, yy = gv * v[e].y - cmp[o][b][e].y;
+                        const float tx = sum[o][b][e].x + yx, ty = sum[o][b][e].y + yy;
+                        cmp[o][b][e].x = (tx - sum[o][b][e].x) - yx;
+                        cmp[o][b][e].y = (ty - sum[o][b][e].y) - yy;
+                        sum[o][b][e].x = tx;
+                        sum[o][b][e].y = ty;
+                    } else {
+                        sum[o][b][e] = mk(fmaf(gv, v[e].x, sum[o][b][e].x), fmaf(gv, v[e].y, sum[o][b][e].y));
+                    }
                 }
         };
         load_g(k0);
@@ -435,12 +450,17 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         };
 #pragma unroll
         for (int b = 0; b < NB_; ++b) {
+            if (b >= a.nb) break;   // (uniform: the barriers below stay matched)
             cx<float> y[NO][E];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    y[o][e] = sum[o][b][e] - cmp[o][b][e];
+                    if constexpr (CS) {
+                        y[o][e] = sum[o][b][e] - cmp[o][b][e];
+                    } else {
+                        y[o][e] = sum[o][b][e];
+                    }
                     if (o == 0 && has_dc && EF::out_pos(t, e) == 0) y[o][e] = mk(0.f, 0.f);
                 }
                 // the last forward pass's placement is the first inverse pass's
@@ -644,17 +664,29 @@ static int fused_slots() {
     return cached;
 }
 
+// Three or four bands per launch (plain sums, prefetch depth 1): compiled
+// at N = 384 and 512, where the slice spectra are the largest and reading
+// them once for four bands instead of twice pays most.
+template <int N, int PF, bool PAR> constexpr bool fused_nb4() { return (N == 384 || N == 512) && PF == 1 && !PAR; }
+
 template <int N, typename S, int PF, bool PAR>
 static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                                int64_t tiles, int kmax) {
     static_assert(FusedShape<N, S>::CPW == FusedShape<N, FusedTiling<N>>::CPW, "variants share the tiling");
-    const int slots = fa.nband == 2 ? fused_slots<N, 2, S, PF, PAR>() : fused_slots<N, 1, S, PF, PAR>();
+    int slots = 0;
+    if (fa.nband > 2) {
+        if constexpr (fused_nb4<N, PF, PAR>()) slots = fused_slots<N, 4, S, PF, PAR>();
+        else return hipErrorInvalidValue;
+    } else {
+        slots = fa.nband == 2 ? fused_slots<N, 2, S, PF, PAR>() : fused_slots<N, 1, S, PF, PAR>();
+    }
     // (two part slots per workgroup with two outputs per tile)
     const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts / (PAR ? 2 : 1));
     FusedDev d;
     d.spec = (const cx<float> *)fa.spec; d.spec_stride = fa.spec_stride;
     d.ghat = (const float *)fa.ghat; d.oct_stride = fa.oct_stride;
-    d.B = fa.B; d.band0 = fa.band0; d.K0 = fa.kcount[0]; d.K1 = fa.kcount[1];
+    d.B = fa.B; d.band0 = fa.band0; d.nb = fa.nband;
+    for (int b = 0; b < 4; ++b) d.Kc[b] = b < fa.nband ? fa.kcount[b] : 0;
     d.acc = (cx<float> *)fa.acc; d.acc_stride = fa.acc_stride;
     d.part = (cx<float> *)fa.part; d.part_stride = fa.part_stride;
     d.zero_dc = fa.zero_dc; d.kahan = fa.kahan;
@@ -667,7 +699,11 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
         hipLaunchKernelGGL(fused_split_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
                            (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W, PAR ? 1 : 0, (int64_t)s0.n_wgs);
     constexpr int NT = FusedShape<N, S>::NT;
-    if (fa.nband == 2)
+    if (fa.nband > 2) {
+        if constexpr (fused_nb4<N, PF, PAR>())
+            hipLaunchKernelGGL((fused_z_kernel<N, 4, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+                               (const cx<float> *)tw);
+    } else if (fa.nband == 2)
         hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     else
@@ -702,7 +738,8 @@ static hipError_t fused_sched(const FusedArgs &fa, const void *tw, hipStream_t s
                               int64_t tiles, int kmax) {
     // variant = 2 * schedule + (prefetch depth 1 ? 1 : 0); schedule 1 = Sched8
     // (N = 384, 512 compile only the Sched8 pair)
-    const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 ? 1 : 2;
+    // (three or four bands per launch: prefetch depth 1 only)
+    const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 || fa.nband > 2 ? 1 : 2;
     if constexpr (HasSched8<N>::value) {
         if (sched == 1)
             return pf == 1 ? fused_launch<N, Sched8<N>, 1, PAR>(fa, tw, st, s0, s1, tiles, kmax)
@@ -756,6 +793,8 @@ int fused_variants(int n) {
 
 bool fused_parity_supported(int n) { return n == 192 || n == 256; }
 
+int fused_max_bands(int n) { return (n == 384 || n == 512) ? 4 : 2; }
+
 // Built-in choice: prefetch depth 2 for one band per launch, 1 for two (the
 // two-band instances of depth 2 spill registers).
 int fused_default_variant(int n, int nband) {
@@ -765,7 +804,7 @@ int fused_default_variant(int n, int nband) {
 }
 
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st) {
-    if (a.nband < 1 || a.nband > 2) return hipErrorInvalidValue;
+    if (a.nband < 1 || a.nband > 4) return hipErrorInvalidValue;
     switch (n) {
 #define X_(N) case N: return fused_t<N>(a, tw_full, st);
         X_(8) X_(12) X_(16) X_(24) X_(32) X_(48) X_(64) X_(96) X_(128) X_(192) X_(256) X_(384) X_(512)

@@ -239,10 +239,11 @@ struct BoxPlan {
     // non-finite source sums seen by the DC reduction since the last query:
     // {count, smallest lookback index} (device, {0, INT32_MAX} when clear)
     int *status = nullptr;
-    char *part = nullptr;        // FP32 form: second parts of split fused tiles, 2 bands
-    int *split_tab = nullptr;    // per band pair slot: tile -> part slot
+    char *part = nullptr;        // FP32 form: second parts of split fused tiles, per band of a launch
+    int *split_tab = nullptr;    // per fused launch of a field: tile -> part slot
     int64_t max_parts = 0, part_stride = 0, tiles = 0;
     int fused_variant = 0, fused_rounds = 1;
+    int fused_bands = 1;         // bands per fused z launch (3-4: plain sums)
     int xy_variant = 0;          // launch shape of the fused xy pass
     int push_group = 2;          // slices per batched forward launch in lc_step
     unsigned long long *maxima = nullptr;
@@ -358,8 +359,8 @@ Layout layout_of(const lc_plan_desc *d) {
         o.sk = take((size_t)K * 8);
         o.status = take(2 * sizeof(int32_t));
         if (d->precision == LC_PREC_FP32) {
-            o.part = take((size_t)2 * fused_parts(n) * n * fused_cpw(n) * 8);
-            o.split_tab = take((size_t)((B + 1) / 2) * fused_tiles(n) * 4);
+            o.part = take((size_t)std::min(B, fused_max_bands(n)) * fused_parts(n) * n * fused_cpw(n) * 8);
+            o.split_tab = take((size_t)B * fused_tiles(n) * 4);
         } else {
             o.part = o.split_tab = 0;
         }
@@ -477,9 +478,9 @@ FusedArgs fused_args(const BoxPlan &bp) {
     FusedArgs fa;
     const int n = bp.n;
     fa.spec = bp.spec; fa.spec_stride = spec_elems(n); fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
-    fa.K = bp.K; fa.B = bp.B; fa.band0 = 0; fa.nband = std::min(2, bp.B);
-    fa.kcount[0] = bp.kcount[0]; fa.kcount[1] = bp.B > 1 ? bp.kcount[1] : 0;
-    fa.acc = bp.acc; fa.acc_stride = spec_elems(n); fa.zero_dc = 1; fa.kahan = 1;
+    fa.K = bp.K; fa.B = bp.B; fa.band0 = 0; fa.nband = bp.fused_bands;
+    for (int j = 0; j < 4; ++j) fa.kcount[j] = j < fa.nband ? bp.kcount[j] : 0;
+    fa.acc = bp.acc; fa.acc_stride = spec_elems(n); fa.zero_dc = 1; fa.kahan = fa.nband <= 2;
     fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
     fa.split_tab = bp.split_tab;
     fa.variant = bp.fused_variant;
@@ -544,7 +545,7 @@ int autotune_box_uncached(lc_plan_t *p, BoxPlan &bp);
 int autotune_box(lc_plan_t *p, BoxPlan &bp) {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    const TuneKey key{dev, bp.n, bp.K, std::min(2, bp.B)};
+    const TuneKey key{dev, bp.n, bp.K, bp.fused_bands};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
@@ -696,8 +697,10 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
             bp.max_parts = fused_parts(x.n);
             bp.part_stride = bp.max_parts * x.n * fused_cpw(x.n);
             bp.tiles = fused_tiles(x.n);
-            bp.fused_variant = fused_default_variant(x.n, std::min(2, x.n_bands));
-        } bp.maxima = (unsigned long long *)(p->ws + o.maxima);
+            bp.fused_bands = std::min(x.n_bands, fused_max_bands(x.n));
+            bp.fused_variant = fused_default_variant(x.n, bp.fused_bands);
+        }
+        bp.maxima = (unsigned long long *)(p->ws + o.maxima);
         bp.tw_half = p->ws + o.tw_half; bp.tw_full = p->ws + o.tw_full; bp.twist = p->ws + o.twist;
         bp.tw64_half = p->ws + o.tw64_half; bp.tw64_full = p->ws + o.tw64_full;
         bp.twist64 = p->ws + o.twist64;
@@ -1018,18 +1021,17 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
         HIPCHK(launch_spec_dc(bp.spec, p->t_f64, se, K, bp.sk, bp.status, bp.head, st));
     if (p->prec == LC_PREC_FP32) {
         for (int b = b0; b < b1;) {
-            const int nb = std::min(2, b1 - b);
-            int *tab = bp.split_tab + (size_t)(b / 2) * bp.tiles;
+            const int nb = std::min(bp.fused_bands, b1 - b);
+            int *tab = bp.split_tab + (size_t)(b / bp.fused_bands) * bp.tiles;
             FusedArgs fa;
             fa.spec = bp.spec; fa.spec_stride = se;
             fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
             fa.K = K; fa.B = bp.B; fa.band0 = b; fa.nband = nb;
-            fa.kcount[0] = bp.kcount[b];
-            fa.kcount[1] = nb > 1 ? bp.kcount[b + 1] : 0;
+            for (int j = 0; j < 4; ++j) fa.kcount[j] = j < nb ? bp.kcount[b + j] : 0;
             fa.acc = bp.acc + (size_t)b * se * cs; fa.acc_stride = se;
             fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
             fa.split_tab = tab;
-            fa.zero_dc = 1; fa.kahan = 1; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
+            fa.zero_dc = 1; fa.kahan = nb <= 2; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             fa.parity = bp.parity() ? 1 : 0;
             fa.ring = bp.head;
             fa.frozen = frozen;
@@ -1440,16 +1442,7 @@ int lc_time_kernel(lc_plan_t *p, int32_t box, int32_t kernel, int32_t reps, doub
             case LC_KERNEL_COL_Y_FWD: return launch_col(n, p->t_f64, 1, true, speck, bp.tw_full, st);
             case LC_KERNEL_COL_Z_FWD: return launch_col(n, p->t_f64, 2, true, speck, bp.tw_full, st);
             case LC_KERNEL_FUSED_Z: {
-                FusedArgs fa;
-                fa.spec = bp.spec; fa.spec_stride = se; fa.ghat = bp.ghat; fa.oct_stride = oct_elems(n);
-                fa.K = bp.K; fa.B = bp.B; fa.band0 = 0; fa.nband = std::min(2, bp.B);
-                fa.kcount[0] = bp.kcount[0]; fa.kcount[1] = bp.B > 1 ? bp.kcount[1] : 0;
-                fa.acc = bp.acc; fa.acc_stride = se; fa.zero_dc = 1; fa.kahan = 1;
-                fa.part = bp.part; fa.part_stride = bp.part_stride; fa.max_parts = bp.max_parts;
-                fa.split_tab = bp.split_tab;
-                fa.variant = bp.fused_variant;
-                fa.rounds = bp.fused_rounds;
-                fa.parity = bp.parity() ? 1 : 0;
+                FusedArgs fa = fused_args(bp);
                 fa.ring = bp.head;
                 return launch_fused_z(n, fa, bp.tw_full, st);
             }
@@ -1495,6 +1488,8 @@ int lc_get_schedule(lc_plan_t *p, int32_t box, lc_schedule *out) {
     out->fused_variant = fused ? bp.fused_variant : -1;
     out->fused_rounds = bp.fused_rounds;
     out->push_group = bp.push_group;
+    out->fused_bands = fused ? bp.fused_bands : -1;
+    out->n_fused_bands = fused ? std::min(bp.B, fused_max_bands(bp.n)) : 0;
     return ok();
 }
 
@@ -1511,6 +1506,9 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     if (s->fused_rounds != 0 && s->fused_rounds != 1) return fail(LC_EINVAL, "fused_rounds must be 0 or 1");
     if (s->push_group < 1 || s->push_group > SrcTab::kMax)
         return fail(LC_EINVAL, "push_group must be in [1, %d]", SrcTab::kMax);
+    const int max_bands = fused ? std::min(bp.B, fused_max_bands(bp.n)) : 0;
+    if (fused ? (s->fused_bands < 1 || s->fused_bands > max_bands) : s->fused_bands != -1)
+        return fail(LC_EINVAL, "fused_bands %d not available (1..%d)", s->fused_bands, max_bands);
     const bool use_xy = s->xy_variant >= 0;
     const bool par = use_xy && xy_parity(bp.n, s->xy_variant);
     if (use_xy != bp.use_xy || par != bp.parity()) {
@@ -1525,7 +1523,10 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     bp.use_xy = use_xy;
     if (use_xy) bp.xy_variant = s->xy_variant;
     bp.dcw = bp.dc_width();
-    if (fused) bp.fused_variant = s->fused_variant;
+    if (fused) {
+        bp.fused_variant = s->fused_variant;
+        bp.fused_bands = s->fused_bands;
+    }
     bp.fused_rounds = s->fused_rounds;
     bp.push_group = s->push_group;
     p->gkey.clear();   // the next lc_step captures the new launch sequence

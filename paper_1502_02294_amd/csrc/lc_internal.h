@@ -101,15 +101,16 @@ hipError_t launch_mac_plain(int n, bool t_f64, void *A, const void *S, const voi
 
 // Fused z pass for FP32: for each column of the y-transformed slices,
 // forward z transform of every slice k < kcount[b], multiply by G^_{k,b},
-// compensated sum over k, inverse z transform, store to acc[b].
+// sum over k (compensated with one or two bands per launch, plain with
+// three or four), inverse z transform, store to acc[b].
 struct FusedArgs {
     const void *spec;        // K slices, stride spec_elems(n)
     int64_t spec_stride;
     const void *ghat;        // slice k band b at ghat + (k*B + b)*oct_stride
     int64_t oct_stride;
     int32_t K, B;            // slices, total bands in ghat layout
-    int32_t band0, nband;    // bands handled by this launch (nband 1 or 2)
-    int32_t kcount[2];       // slices with nonzero kernel, per handled band
+    int32_t band0, nband;    // bands handled by this launch (nband 1..fused_max_bands(n))
+    int32_t kcount[4];       // slices with nonzero kernel, per handled band
     void *acc;               // handled band j at acc + j*acc_stride (complex elements)
     int64_t acc_stride;
     void *part;              // second parts of split tiles: [band j][slot][N*CPW] complex
@@ -133,6 +134,7 @@ struct FusedArgs {
 int fused_variants(int n);   // number of register schedules compiled for n
 bool fused_parity_supported(int n);   // parity-layout input compiled for n
 int fused_default_variant(int n, int nband);   // built-in choice for 1 or 2 bands per launch
+int fused_max_bands(int n);  // bands one fused launch can take: 4 at N = 384, 512, else 2
 hipError_t launch_fused_z(int n, const FusedArgs &a, const void *tw_full, hipStream_t st);
 int64_t fused_tiles(int n);  // column tiles of the fused pass (main + nyq)
 int fused_cpw(int n);        // columns per tile

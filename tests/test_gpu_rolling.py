@@ -115,7 +115,7 @@ def test_rolling_step_after_advance_parity_layout():
             torch.cuda.synchronize()
             assert torch.equal(out[0], J)
         fresh = lc.Plan([box], precision=lc.LC_PREC_FP32, autotune=False)
-        fresh.set_schedule(0, **{k: v for k, v in roll.get_schedule(0).items() if k not in ("n_xy", "n_fused")})
+        fresh.set_schedule(0, **{k: v for k, v in roll.get_schedule(0).items() if k not in ("n_xy", "n_fused", "n_fused_bands")})
         fresh.build_all()
         for k in range(K):
             fresh.push_grid(0, k, grids[t + K - 1 - k])

@@ -371,8 +371,10 @@ def test_schedule_validation():
     box = _box(64, K=2)
     plan = lc.Plan([box], precision=lc.LC_PREC_FP32)
     s = plan.get_schedule(0)
+    assert s["fused_bands"] == s["n_fused_bands"] == 1   # one band at N = 64
     for bad in (dict(xy_variant=s["n_xy"]), dict(xy_variant=-2), dict(fused_variant=s["n_fused"]),
-                dict(fused_rounds=2), dict(push_group=0), dict(push_group=65)):
+                dict(fused_rounds=2), dict(push_group=0), dict(push_group=65),
+                dict(fused_bands=0), dict(fused_bands=2)):
         with pytest.raises(lc.LCError) as ei:
             plan.set_schedule(0, **bad)
         assert ei.value.code == lc.LC_EINVAL
@@ -381,6 +383,7 @@ def test_schedule_validation():
     p64 = lc.Plan([box], precision=lc.LC_PREC_FP64)
     s64 = p64.get_schedule(0)
     assert s64["n_xy"] == 0 and s64["xy_variant"] == -1 and s64["fused_variant"] == -1
+    assert s64["fused_bands"] == -1 and s64["n_fused_bands"] == 0
     with pytest.raises(lc.LCError):
         p64.set_schedule(0, xy_variant=0)
     p64.close()
