@@ -58,6 +58,7 @@ class Box:
     bands: List[Atten]
     sources: List[Tuple[np.ndarray, np.ndarray]]  # per slice (cells int64, lum float64)
     conserve: int = 0
+    rule: int = 0                # mesh kernel: 0 m^3 subpoints, 1 exact cell average
 
     @property
     def n_slices(self) -> int:

@@ -73,10 +73,16 @@ def lib():
         L.or_redshift_at_time.restype = C.c_double
         L.or_build_G_slices.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, ap, C.c_int, dp]
         L.or_near_correction.argtypes = [C.c_int, C.c_double, C.c_int, dp, C.c_int, ap, ip, dp, dp,
-                                         C.c_int, dp]
+                                         C.c_int, dp, C.c_int, C.c_int]
         L.or_dft3_brute.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
         L.or_conv3_brute.argtypes = [C.c_int, dp, dp, dp]
         L.or_num_threads.restype = C.c_int
+        L.or_theta_rect.argtypes = [C.c_double] * 5; L.or_theta_rect.restype = C.c_double
+        L.or_cell_average.argtypes = [ap, C.c_double, dp, C.c_double, C.c_double, C.c_int]
+        L.or_cell_average.restype = C.c_double
+        L.or_G_exact_at.argtypes = [C.c_int, C.c_double, C.c_int, dp, ap, C.c_int, C.c_int, C.c_int,
+                                    C.c_int, dp]
+        L.or_build_G_exact.argtypes = [C.c_int, C.c_double, C.c_int, dp, ap, C.c_int, dp]
         _LIB = L
     return _LIB
 
@@ -161,6 +167,48 @@ def build_G_slices(n: int, L: float, radii, m: int, attens, conserve: int = 0) -
     return G
 
 
+# --- exact cell-averaged kernel (the m -> infinity limit of the subpoint rule) ----------
+
+EXACT_ORDER = 32   # Gauss-Legendre points per piece of the exact cell average
+
+
+def theta_rect(R: float, x0: float, x1: float, y0: float, y1: float) -> float:
+    """Angle of the circle of radius R (centred at the origin) inside the
+    rectangle [x0, x1] x [y0, y1]."""
+    return float(lib().or_theta_rect(R, x0, x1, y0, y1))
+
+
+def cell_average(at, l: float, box, r_lo: float, r_hi: float, ng: int = EXACT_ORDER) -> float:
+    """pref / l^3 times the integral over box = (x0, x1, y0, y1, z0, z1) of
+    phi(r) / (4 pi r^2) on the shell r_lo <= r < r_hi (source at the origin)."""
+    b = np.ascontiguousarray(box, dtype=np.float64)
+    a = _atten(at)
+    return float(lib().or_cell_average(C.byref(a), float(l), _dptr(b), float(r_lo), float(r_hi), int(ng)))
+
+
+def G_exact_at(n: int, L: float, radii, at, disp, ng: int = EXACT_ORDER) -> np.ndarray:
+    """All K exact cell-averaged shell values at one displacement (every image)."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    K = len(radii) - 1
+    out = np.zeros(K)
+    a = _atten(at)
+    rc = lib().or_G_exact_at(n, L, K, _dptr(radii), C.byref(a), int(disp[0]), int(disp[1]), int(disp[2]),
+                             int(ng), _dptr(out))
+    assert rc == 0
+    return out
+
+
+def build_G_exact(n: int, L: float, radii, at, ng: int = EXACT_ORDER) -> np.ndarray:
+    """Dense exact cell-averaged G[k, i, j, x], FP64."""
+    radii = np.ascontiguousarray(radii, dtype=np.float64)
+    K = len(radii) - 1
+    G = np.zeros((K, n, n, n))
+    a = _atten(at)
+    rc = lib().or_build_G_exact(n, L, K, _dptr(radii), C.byref(a), int(ng), _dptr(G))
+    assert rc == 0
+    return G
+
+
 # --- cosmology (Sec. 2.1 Eqs. 4-5; Sec. 3 Eqs. 14-17) ---------------------------------
 
 def cosmic_time(h: float, om: float, z: float) -> float:
@@ -212,10 +260,11 @@ def ngp_cells(n: int, L: float, pos: np.ndarray) -> np.ndarray:
     return (c[:, 0] * n + c[:, 1]) * n + c[:, 2]
 
 
-def near_correction(n: int, L: float, radii, m: int, attens, positioned, R: int) -> np.ndarray:
+def near_correction(n: int, L: float, radii, m: int, attens, positioned, R: int, rule: int = 0) -> np.ndarray:
     """Particle-mesh near-field correction (Sec. 4) of positioned sources:
     positioned[k] = (pos (n_k, 3) in length units, lum (n_k,)); attens[k]
-    the radial factor of slice k. Returns the N^3 correction grid."""
+    the radial factor of slice k; rule 1 for a mesh kernel of exact cell
+    averages. Returns the N^3 correction grid."""
     radii = np.ascontiguousarray(radii, dtype=np.float64)
     K = len(radii) - 1
     assert len(attens) == K and len(positioned) == K
@@ -229,7 +278,7 @@ def near_correction(n: int, L: float, radii, m: int, attens, positioned, R: int)
     arr = (_Atten * K)(*[_atten(a) for a in attens])
     corr = np.zeros(n ** 3)
     rc = lib().or_near_correction(n, L, K, _dptr(radii), m, arr, _iptr(off), _dptr(pos.ravel()), _dptr(lum),
-                                  int(R), _dptr(corr))
+                                  int(R), _dptr(corr), int(rule), EXACT_ORDER)
     assert rc == 0
     return corr.reshape(n, n, n)
 

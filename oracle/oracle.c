@@ -591,7 +591,8 @@ int or_build_G_slices(int N, double L, int K, const double *radii, int m,
  * c_s = round(x_s / l) in the mesh field. For target nodes c_s + o with
  * 0 < max|o_d| <= R the primary-image part of the mesh kernel, the
  * m^3-subpoint average over the image u = 0 at displacement o, is replaced
- * by the retarded kernel at the exact distance |(c_s + o) l - x_s|:
+ * by the retarded kernel at the exact distance |(c_s + o) l - x_s|
+ * (with rule 1, the primary image's exact cell average is replaced):
  *   corr(c_s + o) += L (F_k(rho) - Gprim_k(o)).
  * Slice k of the K point lists uses at[k]. Plain sequential FP64 sums. */
 static double or_G_primary(const kern_t *kp, int k, int o0, int o1, int o2)
@@ -611,8 +612,13 @@ static double or_G_primary(const kern_t *kp, int k, int o0, int o1, int o2)
     return acc;
 }
 
+double or_cell_average(const or_atten *at, double l, const double *B, double rlo, double rhi, int ng);
+
+/* rule 1: the mesh kernel is the exact cell average (or_cell_average of the
+ * primary image cell) instead of the subpoint average */
 int or_near_correction(int N, double L, int K, const double *radii, int m, const or_atten *at,
-                       const int64_t *off, const double *pos, const double *lum, int R, double *corr)
+                       const int64_t *off, const double *pos, const double *lum, int R, double *corr,
+                       int rule, int ng)
 {
     const double l = L / N;
     memset(corr, 0, sizeof(double) * (int64_t)N * N * N);
@@ -640,9 +646,241 @@ int or_near_correction(int N, double L, int K, const double *radii, int m, const
                 double F = 0.0;
                 if (rho >= radii[k] && rho < radii[k + 1])
                     F = at[k].prefactor * or_phi(&at[k], rho) / (4.0 * OR_PI * rho * rho);
-                corr[cell] += lum[s] * (F - or_G_primary(&kp, k, o0, o1, o2));
+                double Gp;
+                if (rule == 1) {
+                    double B[6] = { (o0 - 0.5) * l, (o0 + 0.5) * l, (o1 - 0.5) * l, (o1 + 0.5) * l,
+                                    (o2 - 0.5) * l, (o2 + 0.5) * l };
+                    Gp = or_cell_average(&at[k], l, B, radii[k], radii[k + 1], ng);
+                } else {
+                    Gp = or_G_primary(&kp, k, o0, o1, o2);
+                }
+                corr[cell] += lum[s] * (F - Gp);
             }
         }
+    }
+    return 0;
+}
+
+/* ---- exact cell-averaged kernel ----------------------------------------
+ * The m -> infinity limit of the subpoint average (the "exact cell
+ * integral" refinement of the near-source treatment of Sec. 4). For an image
+ * cell B = [x0,x1] x [y0,y1] x [z0,z1] of the unit source at the origin and
+ * the shell [r_lo, r_hi) of Eq. 10:
+ *
+ *   G_B = pref / l^3 * int_B phi(|x|) / (4 pi |x|^2) [r_lo <= |x| < r_hi] d^3x.
+ *
+ * Cylindrical coordinates about the z axis (x = R cos t, y = R sin t,
+ * d^3x = R dR dt dz) and z = R tan s (so |x| = R / cos s and
+ * dz / |x|^2 = ds / R) turn it into
+ *
+ *   G_B = pref / (4 pi l^3) int_R Theta(R) S(R) dR,
+ *   Theta(R) = angle of the circle of radius R inside [x0,x1] x [y0,y1],
+ *   S(R)     = int_{A(R)} phi(R / cos s) ds,
+ *   A(R)     = {s in (-pi/2, pi/2): z0 <= R tan s <= z1, r_lo <= R / cos s < r_hi}.
+ *
+ * With phi = 1, S(R) is the length of A(R) and G_B is a single quadrature
+ * in R. R is split wherever Theta or A(R) changes form (edge and corner
+ * distances of the rectangle, r_lo, r_hi, sqrt(r^2 - z^2) for the z faces);
+ * each piece is integrated by ng-point Gauss-Legendre after the substitution
+ * R = Ra + (Rb - Ra)(1 - cos u)/2, u in [0, pi], which turns the square-root
+ * behaviour at the piece ends into smooth integrands. A piece starting at
+ * R = 0 (cells around the source) takes the tanh-sinh rule instead: there
+ * S(R) carries the r^p cusp of phi at r = 0 (S(R) ~ S(0) - C R^p), an
+ * algebraic end singularity that the substitution does not remove. The phi
+ * integral over
+ * each interval of A(R) (kinds 1 and 2, whose support ends are folded into
+ * r_hi) is an ng-point Gauss-Legendre rule. */
+
+/* angle of the circle of radius R inside [a,b] x [c,d], 0 <= a < b, 0 <= c < d
+ * (first quadrant): x = R cos t in [a,b] and y = R sin t in [c,d] */
+static double theta_quadrant(double R, double a, double b, double c, double d)
+{
+    double tx0 = acos(fmin(1.0, a / R)), tx1 = acos(fmin(1.0, b / R));
+    double ty0 = asin(fmin(1.0, c / R)), ty1 = asin(fmin(1.0, d / R));
+    double lo = fmax(tx1, ty0), hi = fmin(tx0, ty1);
+    return hi > lo ? hi - lo : 0.0;
+}
+
+/* Theta(R): the rectangle's parts in the four quadrants, each reflected into
+ * the first one. */
+double or_theta_rect(double R, double x0, double x1, double y0, double y1)
+{
+    if (!(R > 0.0)) return 0.0;
+    double t = 0.0;
+    for (int sx = 0; sx < 2; ++sx)
+    for (int sy = 0; sy < 2; ++sy) {
+        double a = sx == 0 ? fmax(x0, 0.0) : fmax(-x1, 0.0);
+        double b = sx == 0 ? x1 : -x0;
+        double c = sy == 0 ? fmax(y0, 0.0) : fmax(-y1, 0.0);
+        double d = sy == 0 ? y1 : -y0;
+        if (b > a && d > c) t += theta_quadrant(R, a, b, c, d);
+    }
+    return t;
+}
+
+/* S(R) for R > 0; rhi is already capped at the end of phi's support */
+static double s_of_R(const or_atten *at, double R, double z0, double z1, double rlo, double rhi,
+                     int ng, const double *gx, const double *gw)
+{
+    if (R >= rhi) return 0.0;
+    double tH = acos(R / rhi);
+    double tL = R < rlo ? acos(R / rlo) : 0.0;
+    double ta = atan2(z0, R), tb = atan2(z1, R);
+    double iv[2][2] = { { fmax(ta, -tH), fmin(tb, -tL) }, { fmax(ta, tL), fmin(tb, tH) } };
+    double acc = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        double lo = iv[i][0], hi = iv[i][1];
+        if (!(hi > lo)) continue;
+        if (at->kind == 0) { acc += hi - lo; continue; }
+        /* tanh-sinh in s: for small R, phi(R / cos s) changes within thin
+         * layers at the interval ends (|s| near pi/2), which the rule's
+         * end clustering resolves. s = mid + hw tanh(y), y = (pi/2) sinh t;
+         * the distance to the nearer end, hw / (1 + e^{2|y|}), is formed
+         * directly so that cos s keeps its relative accuracy there. */
+        double hw = 0.5 * (hi - lo), mid = 0.5 * (hi + lo), q = 0.0;
+        const double h = 2.0 / ng;
+        const int nt = (int)(4.0 / h);
+        for (int j = -nt; j <= nt; ++j) {
+            double t = j * h, y = 0.5 * OR_PI * sinh(t);
+            double dist = 2.0 * hw / (1.0 + exp(2.0 * fabs(y)));   /* to the end on y's side */
+            double sv = y >= 0.0 ? hi - dist : lo + dist;
+            double cy = cosh(y);
+            double w = h * hw * 0.5 * OR_PI * cosh(t) / (cy * cy);
+            if (!(w > 0.0)) continue;
+            q += w * or_phi(at, R / cos(sv));
+        }
+        acc += q;
+    }
+    return acc;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* G_B for the box B = {x0,x1,y0,y1,z0,z1} (length units, source at the
+ * origin), shell [rlo, rhi), cell side l, ng-point rules (ng <= 64). */
+double or_cell_average(const or_atten *at, double l, const double *B, double rlo, double rhi, int ng)
+{
+    if (ng < 2 || ng > 64) return NAN;
+    double sup = phi_support_end(at);
+    if (rhi > sup) rhi = sup;
+    if (!(rhi > rlo)) return 0.0;
+    const double x0 = B[0], x1 = B[1], y0 = B[2], y1 = B[3], z0 = B[4], z1 = B[5];
+    double nx = x0 > 0.0 ? x0 : (x1 < 0.0 ? -x1 : 0.0);
+    double ny = y0 > 0.0 ? y0 : (y1 < 0.0 ? -y1 : 0.0);
+    double Rmin = hypot(nx, ny);
+    double Rmax = fmin(hypot(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))), rhi);
+    if (!(Rmax > Rmin)) return 0.0;
+    double br[32];
+    int nb = 0;
+    br[nb++] = Rmin;
+    br[nb++] = Rmax;
+    const double xs[2] = { x0, x1 }, ys[2] = { y0, y1 }, zs[2] = { z0, z1 }, rs[2] = { rlo, rhi };
+    double cand[16];
+    int nc = 0;
+    for (int i = 0; i < 2; ++i) { cand[nc++] = fabs(xs[i]); cand[nc++] = fabs(ys[i]); }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) cand[nc++] = hypot(xs[i], ys[j]);
+    cand[nc++] = rlo;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (rs[i] > fabs(zs[j])) cand[nc++] = sqrt(rs[i] * rs[i] - zs[j] * zs[j]);
+    for (int i = 0; i < nc; ++i)
+        if (cand[i] > Rmin && cand[i] < Rmax) br[nb++] = cand[i];
+    qsort(br, nb, sizeof(double), cmp_double);
+    double gx[64], gw[64];
+    gauss_legendre(ng, gx, gw);
+    double acc = 0.0;
+    for (int p = 0; p + 1 < nb; ++p) {
+        double Ra = br[p], Rb = br[p + 1];
+        if (!(Rb > Ra)) continue;
+        double q = 0.0;
+        if (Ra == 0.0) {
+            /* tanh-sinh: R = Rb / (1 + e^{-2y}), y = (pi/2) sinh t, t in
+             * [-4, 4] with step 1/(ng/2); dR/dt = Rb (pi/2) cosh t /
+             * (2 cosh^2 y) */
+            const double h = 2.0 / ng;
+            const int nt = (int)(4.0 / h);
+            for (int i = -nt; i <= nt; ++i) {
+                double t = i * h, y = 0.5 * OR_PI * sinh(t);
+                double R = Rb / (1.0 + exp(-2.0 * y));
+                double cy = cosh(y);
+                double w = h * Rb * 0.5 * OR_PI * cosh(t) / (2.0 * cy * cy);
+                if (!(R > 0.0) || !(w > 0.0)) continue;
+                q += w * or_theta_rect(R, x0, x1, y0, y1) * s_of_R(at, R, z0, z1, rlo, rhi, ng, gx, gw);
+            }
+            acc += q;
+            continue;
+        }
+        for (int j = 0; j < ng; ++j) {
+            double u = 0.5 * OR_PI * (gx[j] + 1.0);
+            double R = Ra + 0.5 * (Rb - Ra) * (1.0 - cos(u));
+            double jac = 0.5 * OR_PI * 0.5 * (Rb - Ra) * sin(u);
+            q += gw[j] * jac * or_theta_rect(R, x0, x1, y0, y1) * s_of_R(at, R, z0, z1, rlo, rhi, ng, gx, gw);
+        }
+        acc += q;
+    }
+    return at->prefactor * acc / (4.0 * OR_PI * l * l * l);
+}
+
+/* All K exact shell values at displacement (d0,d1,d2) (cells), every
+ * periodic image whose cell can reach [r_0, r_K) (the culling of
+ * kern_accumulate). */
+static void exact_accumulate(int N, double L, int K, const double *radii, const or_atten *at,
+                             int d0, int d1, int d2, int ng, double *outK)
+{
+    const double l = L / N;
+    const int U = (int)ceil(radii[K] / L) + 1;
+    int dd[3] = { ((d0 % N) + N) % N, ((d1 % N) + N) % N, ((d2 % N) + N) % N };
+    for (int u0 = -U; u0 <= U; ++u0)
+    for (int u1 = -U; u1 <= U; ++u1)
+    for (int u2 = -U; u2 <= U; ++u2) {
+        int64_t cx[3] = { dd[0] + (int64_t)u0 * N, dd[1] + (int64_t)u1 * N, dd[2] + (int64_t)u2 * N };
+        double B[6], mn2 = 0.0, mx2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double lo = ((double)cx[a] - 0.5) * l, hi = ((double)cx[a] + 0.5) * l;
+            B[2 * a] = lo; B[2 * a + 1] = hi;
+            double near = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0), far = fmax(fabs(lo), fabs(hi));
+            mn2 += near * near; mx2 += far * far;
+        }
+        if (sqrt(mn2) >= radii[K] || sqrt(mx2) <= radii[0]) continue;
+        for (int k = 0; k < K; ++k) {
+            if (sqrt(mn2) >= radii[k + 1] || sqrt(mx2) <= radii[k]) continue;
+            outK[k] += or_cell_average(at, l, B, radii[k], radii[k + 1], ng);
+        }
+    }
+}
+
+int or_G_exact_at(int N, double L, int K, const double *radii, const or_atten *at,
+                  int d0, int d1, int d2, int ng, double *outK)
+{
+    if (K < 1 || ng < 2 || ng > 64) return -1;
+    memset(outK, 0, sizeof(double) * K);
+    exact_accumulate(N, L, K, radii, at, d0, d1, d2, ng, outK);
+    return 0;
+}
+
+/* Dense exact kernel G[k][i][j][kx] (no rescaling: the exact cell average
+ * already sums to the shell integral over the cells reached). */
+int or_build_G_exact(int N, double L, int K, const double *radii, const or_atten *at, int ng, double *G)
+{
+    if (K < 1 || ng < 2 || ng > 64) return -1;
+    const int64_t n3 = (int64_t)N * N * N;
+    memset(G, 0, sizeof(double) * n3 * K);
+    #pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * K);
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t c = 0; c < n3; ++c) {
+            int i = (int)(c / ((int64_t)N * N)), j = (int)((c / N) % N), x = (int)(c % N);
+            memset(tmp, 0, sizeof(double) * K);
+            exact_accumulate(N, L, K, radii, at, i, j, x, ng, tmp);
+            for (int k = 0; k < K; ++k) G[(int64_t)k * n3 + c] = tmp[k];
+        }
+        free(tmp);
     }
     return 0;
 }
