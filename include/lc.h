@@ -92,7 +92,11 @@ typedef struct {
     int32_t supersample;  /* m: 1 (node rule) .. 8 subpoints per axis     */
     int32_t conserve;     /* 1: rescale G_{k,b} so l^3 sum_c G = shell
                              integral of phi_b over [r_k, r_{k+1})         */
-    int32_t reserved;     /* must be 0                                    */
+    int32_t rule;         /* mesh kernel G_{k,b} at a cell (Eq. 10 over the
+                             cell): 0 = average over m^3 subpoints
+                             (supersample m); 1 = exact cell average, the
+                             m -> infinity limit (supersample unused; build
+                             cost ~20-100x rule 0)                        */
     double box;           /* L, same length unit as radii                 */
     const double *radii;  /* K+1 strictly increasing, r_0 >= 0 (host);
                              slice k <-> shell [r_k, r_{k+1}), k = 0 the

@@ -621,10 +621,26 @@ int or_near_correction(int N, double L, int K, const double *radii, int m, const
                        int rule, int ng)
 {
     const double l = L / N;
+    const int D = 2 * R + 1;
     memset(corr, 0, sizeof(double) * (int64_t)N * N * N);
+    double *Gtab = (double *)malloc(sizeof(double) * D * D * D);
+    if (!Gtab) return -1;
     for (int k = 0; k < K; ++k) {
         kern_t kp;
-        if (kern_init(&kp, N, L, K, radii, m, &at[k])) return -1;
+        if (kern_init(&kp, N, L, K, radii, m, &at[k])) { free(Gtab); return -1; }
+        /* the primary image's mesh kernel at every offset of slice k (it
+         * depends on the offset only) */
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int t = 0; t < D * D * D; ++t) {
+            int o0 = t / (D * D) - R, o1 = (t / D) % D - R, o2 = t % D - R;
+            if (rule == 1) {
+                double B[6] = { (o0 - 0.5) * l, (o0 + 0.5) * l, (o1 - 0.5) * l, (o1 + 0.5) * l,
+                                (o2 - 0.5) * l, (o2 + 0.5) * l };
+                Gtab[t] = or_cell_average(&at[k], l, B, radii[k], radii[k + 1], ng);
+            } else {
+                Gtab[t] = or_G_primary(&kp, k, o0, o1, o2);
+            }
+        }
         for (int64_t s = off[k]; s < off[k + 1]; ++s) {
             double c[3];
             for (int d = 0; d < 3; ++d) c[d] = floor(pos[3 * s + d] / l + 0.5);
@@ -646,18 +662,12 @@ int or_near_correction(int N, double L, int K, const double *radii, int m, const
                 double F = 0.0;
                 if (rho >= radii[k] && rho < radii[k + 1])
                     F = at[k].prefactor * or_phi(&at[k], rho) / (4.0 * OR_PI * rho * rho);
-                double Gp;
-                if (rule == 1) {
-                    double B[6] = { (o0 - 0.5) * l, (o0 + 0.5) * l, (o1 - 0.5) * l, (o1 + 0.5) * l,
-                                    (o2 - 0.5) * l, (o2 + 0.5) * l };
-                    Gp = or_cell_average(&at[k], l, B, radii[k], radii[k + 1], ng);
-                } else {
-                    Gp = or_G_primary(&kp, k, o0, o1, o2);
-                }
+                double Gp = Gtab[((o0 + R) * D + (o1 + R)) * D + (o2 + R)];
                 corr[cell] += lum[s] * (F - Gp);
             }
         }
     }
+    free(Gtab);
     return 0;
 }
 
@@ -683,7 +693,8 @@ int or_near_correction(int N, double L, int K, const double *radii, int m, const
  * distances of the rectangle, r_lo, r_hi, sqrt(r^2 - z^2) for the z faces);
  * each piece is integrated by ng-point Gauss-Legendre after the substitution
  * R = Ra + (Rb - Ra)(1 - cos u)/2, u in [0, pi], which turns the square-root
- * behaviour at the piece ends into smooth integrands. A piece starting at
+ * behaviour at the piece ends into smooth integrands, bisected until the
+ * halves agree with the whole. A piece starting at
  * R = 0 (cells around the source) takes the tanh-sinh rule instead: there
  * S(R) carries the r^p cusp of phi at r = 0 (S(R) ~ S(0) - C R^p), an
  * algebraic end singularity that the substitution does not remove. The phi
@@ -760,6 +771,46 @@ static int cmp_double(const void *a, const void *b)
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+typedef struct {
+    const or_atten *at;
+    double x0, x1, y0, y1, z0, z1, rlo, rhi;
+    int ng;
+    const double *gx, *gw;
+} cell_ctx;
+
+/* ng-point Gauss-Legendre rule for int_a^b Theta(R) S(R) dR after
+ * R = a + (b - a)(1 - cos u)/2 */
+static double piece_gl(const cell_ctx *c, double a, double b)
+{
+    double q = 0.0;
+    for (int j = 0; j < c->ng; ++j) {
+        double u = 0.5 * OR_PI * (c->gx[j] + 1.0);
+        double R = a + 0.5 * (b - a) * (1.0 - cos(u));
+        double jac = 0.5 * OR_PI * 0.5 * (b - a) * sin(u);
+        q += c->gw[j] * jac * or_theta_rect(R, c->x0, c->x1, c->y0, c->y1) *
+             s_of_R(c->at, R, c->z0, c->z1, c->rlo, c->rhi, c->ng, c->gx, c->gw);
+    }
+    return q;
+}
+
+/* Adaptive bisection: the two halves replace the whole until they agree
+ * with it to tol (absolute: a small multiple of the rounding level of the
+ * whole cell's value), after at least two levels (an early agreement of
+ * two poor estimates is not taken). A piece is analytic inside, but a
+ * breakpoint just outside it (a shell radius close to an edge distance,
+ * say) slows the rule's convergence; halving towards it restores it. */
+static double piece_adapt(const cell_ctx *c, double a, double b, double whole, double tol, int depth,
+                          int *budget)
+{
+    double m = 0.5 * (a + b);
+    double lq = piece_gl(c, a, m), rq = piece_gl(c, m, b);
+    double two = lq + rq;
+    if (depth >= 48 || *budget <= 0 || (depth >= 2 && fabs(two - whole) <= tol)) return two;
+    *budget -= 2;
+    return piece_adapt(c, a, m, lq, 0.5 * tol, depth + 1, budget) +
+           piece_adapt(c, m, b, rq, 0.5 * tol, depth + 1, budget);
+}
+
 /* G_B for the box B = {x0,x1,y0,y1,z0,z1} (length units, source at the
  * origin), shell [rlo, rhi), cell side l, ng-point rules (ng <= 64). */
 double or_cell_average(const or_atten *at, double l, const double *B, double rlo, double rhi, int ng)
@@ -793,6 +844,12 @@ double or_cell_average(const or_atten *at, double l, const double *B, double rlo
     qsort(br, nb, sizeof(double), cmp_double);
     double gx[64], gw[64];
     gauss_legendre(ng, gx, gw);
+    cell_ctx cc = { at, x0, x1, y0, y1, z0, z1, rlo, rhi, ng, gx, gw };
+    /* scale of the whole cell's value (plain rule on every piece) */
+    double est = 0.0;
+    for (int p = 0; p + 1 < nb; ++p)
+        if (br[p + 1] > br[p]) est += fabs(piece_gl(&cc, br[p], br[p + 1]));
+    const double tol = 1e-14 * est;
     double acc = 0.0;
     for (int p = 0; p + 1 < nb; ++p) {
         double Ra = br[p], Rb = br[p + 1];
@@ -815,13 +872,8 @@ double or_cell_average(const or_atten *at, double l, const double *B, double rlo
             acc += q;
             continue;
         }
-        for (int j = 0; j < ng; ++j) {
-            double u = 0.5 * OR_PI * (gx[j] + 1.0);
-            double R = Ra + 0.5 * (Rb - Ra) * (1.0 - cos(u));
-            double jac = 0.5 * OR_PI * 0.5 * (Rb - Ra) * sin(u);
-            q += gw[j] * jac * or_theta_rect(R, x0, x1, y0, y1) * s_of_R(at, R, z0, z1, rlo, rhi, ng, gx, gw);
-        }
-        acc += q;
+        int budget = 512;
+        acc += piece_adapt(&cc, Ra, Rb, piece_gl(&cc, Ra, Rb), tol, 0, &budget);
     }
     return at->prefactor * acc / (4.0 * OR_PI * l * l * l);
 }

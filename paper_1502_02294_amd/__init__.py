@@ -40,7 +40,7 @@ EXPORTED = ["lc_workspace_bytes", "lc_plan", "lc_build_greens", "lc_push_sources
 
 class lc_box_desc(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_slices", C.c_int32), ("n_bands", C.c_int32),
-                ("supersample", C.c_int32), ("conserve", C.c_int32), ("reserved", C.c_int32),
+                ("supersample", C.c_int32), ("conserve", C.c_int32), ("rule", C.c_int32),
                 ("box", C.c_double), ("radii", C.POINTER(C.c_double))]
 
 
@@ -151,10 +151,10 @@ def _check(rc: int):
 # ---- descriptor helpers -------------------------------------------------------------
 
 def make_box_desc(n: int, box: float, radii, n_bands: int = 1, supersample: int = 1,
-                  conserve: int = 0):
+                  conserve: int = 0, rule: int = 0):
     """Returns (desc, keepalive) with radii held in a ctypes double array."""
     r = (C.c_double * len(radii))(*[float(v) for v in radii])
-    d = lc_box_desc(int(n), len(radii) - 1, int(n_bands), int(supersample), int(conserve), 0,
+    d = lc_box_desc(int(n), len(radii) - 1, int(n_bands), int(supersample), int(conserve), int(rule),
                     float(box), C.cast(r, C.POINTER(C.c_double)))
     return d, r
 
@@ -339,7 +339,7 @@ class Plan:
         descs = []
         for b in self.boxes:
             d, r = make_box_desc(b.n, b.box, b.radii, len(b.bands), b.supersample,
-                                 getattr(b, "conserve", 0))
+                                 getattr(b, "conserve", 0), getattr(b, "rule", 0))
             descs.append(d)
             self._keep.append(r)
         probe, arr = make_plan_desc(descs, precision)

@@ -22,6 +22,185 @@ __device__ __forceinline__ double phi_eval(int kind, double r, double a, double 
     return r <= cut ? v : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Exact cell average (rule 1)
+//
+// For an image cell [x0,x1] x [y0,y1] x [z0,z1] of the unit source at the
+// origin, cylindrical coordinates about the z axis (radius R) and
+// w = asinh(z / R) (so r = R cosh w and dz / r^2 = dw / (R cosh w)) give
+//   pref / l^3 int_cell phi(r) / (4 pi r^2) [r_lo <= r < r_sup] d^3x
+//     = pref / (4 pi l^3) int Q(R) V(R) dR,
+//   Q(R) = angle of the circle of radius R inside [x0,x1] x [y0,y1],
+//   V(R) = int phi(R cosh w) / cosh w dw over w in [asinh(z0/R), asinh(z1/R)]
+//          with R cosh w in [r_lo, r_sup).
+// Q is formed by inclusion-exclusion over the rectangle's corners of the
+// arcs {R cos t >= a} and {R sin t >= b}; V is atan(sinh w) at the interval
+// ends for phi = 1, else a 16-point rule on pieces of at most 2 in w (|w|
+// <= 40: the weight 1 / cosh w is below 1e-17 beyond). The R integral is
+// split where Q or V change form (edge and corner distances of the
+// rectangle, r_lo, r_sup, sqrt(r^2 - z^2) for the z faces); each piece takes
+// the 16-point rule after R = Ra + (Rb - Ra)(1 - cos u) / 2, which smooths the
+// square-root behaviour at piece ends, on parts graded towards any such
+// point that lies just outside it. In the cell holding the source,
+// V(R) ~ V(0) - C R^p near R = 0 (the r^p cusp of phi at r = 0), so the
+// piece from R = 0 is split geometrically at Rb 2^-j, j < 50, each part
+// with the same substitution.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double arc_overlap(double a, double b, double c, double d) {
+    const double lo = fmax(a, c), hi = fmin(b, d);
+    return hi > lo ? hi - lo : 0.0;
+}
+
+// angle of {t : R cos t >= a and R sin t >= b}: the arc [-al, al] against
+// the arc [be, pi - be] (and its copy one turn lower)
+__device__ double arc_quarter(double R, double a, double b) {
+    const double pi = 3.141592653589793238;
+    const double al = acos(fmin(1.0, fmax(-1.0, a / R)));
+    const double be = asin(fmin(1.0, fmax(-1.0, b / R)));
+    return arc_overlap(-al, al, be, pi - be) + arc_overlap(-al, al, be - 2.0 * pi, -pi - be);
+}
+
+__device__ double circle_in_rect(double R, double x0, double x1, double y0, double y1) {
+    return arc_quarter(R, x0, y0) - arc_quarter(R, x1, y0) - arc_quarter(R, x0, y1) + arc_quarter(R, x1, y1);
+}
+
+__device__ double exact_v(const ExactRule &e, double R, double z0, double z1) {
+    if (!(R < e.r_sup)) return 0.0;
+    const double wH = acosh(e.r_sup / R), wL = R < e.r_lo ? acosh(e.r_lo / R) : 0.0;
+    const double wa = asinh(z0 / R), wb = asinh(z1 / R);
+    double acc = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        double lo = side ? fmax(wa, wL) : fmax(wa, -wH);
+        double hi = side ? fmin(wb, wH) : fmin(wb, -wL);
+        if (!(hi > lo)) continue;
+        if (e.kind == 0) {
+            acc += atan(sinh(hi)) - atan(sinh(lo));
+            continue;
+        }
+        lo = fmax(lo, -40.0);
+        hi = fmin(hi, 40.0);
+        if (!(hi > lo)) continue;
+        const int pieces = (int)ceil((hi - lo) * 0.5);
+        const double len = (hi - lo) / pieces;
+        for (int q = 0; q < pieces; ++q) {
+            const double w0 = lo + q * len;
+            double sq = 0.0;
+            for (int j = 0; j < 16; ++j) {
+                const double w = w0 + len * e.gx[j], ch = cosh(w), r = R * ch;
+                const double v = e.a * exp(-pow(r / e.s, e.p)) - e.c;
+                const double ph = (e.kind == 1 && v < 0.0) ? 0.0 : v;   // (kind 2: r < r_sup <= cut)
+                sq += e.gw[j] * ph / ch;
+            }
+            acc += len * sq;
+        }
+    }
+    return acc;
+}
+
+__device__ double cell_exact(const ExactRule &e, double x0, double x1, double y0, double y1, double z0, double z1) {
+    if (!(e.r_sup > e.r_lo)) return 0.0;
+    const double nx = x0 > 0.0 ? x0 : (x1 < 0.0 ? -x1 : 0.0);
+    const double ny = y0 > 0.0 ? y0 : (y1 < 0.0 ? -y1 : 0.0);
+    const double Rmin = sqrt(nx * nx + ny * ny);
+    const double fx = fmax(fabs(x0), fabs(x1)), fy = fmax(fabs(y0), fabs(y1));
+    const double Rmax = fmin(sqrt(fx * fx + fy * fy), e.r_sup);
+    if (!(Rmax > Rmin)) return 0.0;
+    // every R where Q or V may change form (sing), and those inside the
+    // range, sorted by insertion (br)
+    double sing[20], br[20];
+    int ns = 0, nb = 0;
+    auto add = [&](double v) {
+        sing[ns++] = v;
+        if (!(v > Rmin && v < Rmax)) return;
+        int i = nb++;
+        while (i > 0 && br[i - 1] > v) { br[i] = br[i - 1]; --i; }
+        br[i] = v;
+    };
+    const double xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1}, rs[2] = {e.r_lo, e.r_sup};
+    for (int i = 0; i < 2; ++i) {
+        add(fabs(xs[i]));
+        add(fabs(ys[i]));
+        for (int j = 0; j < 2; ++j) {
+            add(sqrt(xs[i] * xs[i] + ys[j] * ys[j]));
+            if (rs[i] > fabs(zs[j])) add(sqrt(rs[i] * rs[i] - zs[j] * zs[j]));
+        }
+    }
+    add(e.r_lo);
+    add(e.r_sup);
+    add(0.0);
+    const bool source_cell = nx == 0.0 && ny == 0.0 && z0 <= 0.0 && z1 >= 0.0;
+    // 16-point rule on [lo, hi] after the cosine substitution
+    auto piece = [&](double lo, double hi) {
+        const double pi = 3.141592653589793238;
+        double sq = 0.0;
+        for (int j = 0; j < 16; ++j) {
+            const double u = pi * e.gx[j];
+            const double R = lo + 0.5 * (hi - lo) * (1.0 - cos(u));
+            const double jac = pi * 0.5 * (hi - lo) * sin(u);
+            sq += e.gw[j] * jac * circle_in_rect(R, x0, x1, y0, y1) * exact_v(e, R, z0, z1);
+        }
+        return sq;
+    };
+    double acc = 0.0;
+    double Ra = Rmin;
+    for (int pc = 0; pc <= nb; ++pc) {
+        const double Rb = pc < nb ? br[pc] : Rmax;
+        if (!(Rb > Ra)) continue;
+        if (Ra == 0.0 && source_cell) {
+            // (the top piece keeps the substitution: R = Rb may be a square-root end)
+            double hi = Rb;
+            for (int g = 0; g < 50; ++g) {
+                acc += piece(0.5 * hi, hi);
+                hi *= 0.5;
+            }
+        } else {
+            // A change of form just outside the piece, at distance dl < len
+            // from Ra (a shell radius close to an edge distance, say), slows
+            // the rule's convergence. The piece is then halved, and the half
+            // at Ra is cut into parts graded towards it: [Ra, Ra + dl], then
+            // parts as long as their distance to Ra (which, being a piece
+            // end, may itself be such a point), up to the middle. The same
+            // towards Rb with dr.
+            double dl = 1e300, dr = 1e300;
+            for (int i = 0; i < ns; ++i) {
+                if (sing[i] < Ra) dl = fmin(dl, Ra - sing[i]);
+                if (sing[i] > Rb) dr = fmin(dr, sing[i] - Rb);
+            }
+            const double len = Rb - Ra;
+            if (dl >= len && dr >= len) {
+                acc += piece(Ra, Rb);
+            } else {
+                const double mid = Ra + 0.5 * len;
+                double lo = Ra;
+                if (dl < mid - lo) {
+                    acc += piece(lo, lo + dl);
+                    lo += dl;
+                    for (int g = 0; g < 64 && lo - Ra < mid - lo; ++g) {
+                        const double d = lo - Ra;
+                        acc += piece(lo, lo + d);
+                        lo += d;
+                    }
+                }
+                acc += piece(lo, mid);
+                double hi = Rb;
+                if (dr < hi - mid) {
+                    acc += piece(hi - dr, hi);
+                    hi -= dr;
+                    for (int g = 0; g < 64 && Rb - hi < hi - mid; ++g) {
+                        const double d = Rb - hi;
+                        acc += piece(hi - d, hi);
+                        hi -= d;
+                    }
+                }
+                acc += piece(mid, hi);
+            }
+        }
+        Ra = Rb;
+    }
+    const double four_pi = 12.566370614359172954;
+    return e.pref * acc / (four_pi * e.l * e.l * e.l);
+}
+
 __global__ __launch_bounds__(256) void greens_build_kernel(BuildArgs a) {
     const int n = a.n, H = n / 2 + 1;
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,6 +227,10 @@ __global__ __launch_bounds__(256) void greens_build_kernel(BuildArgs a) {
                 const double dmin = sqrt(nr0 * nr0 + nr1 * nr1 + nr2 * nr2);
                 const double dmax = sqrt(fr0 * fr0 + fr1 * fr1 + fr2 * fr2);
                 if (dmin > a.r_hi + margin || dmax < a.r_lo - margin) continue;
+                if (a.rule == 1) {
+                    acc += cell_exact(a.ex, lo0, hi0, lo1, hi1, lo2, hi2);
+                    continue;
+                }
                 if (a.self_pair && x0 == 0 && x1 == 0 && x2 == 0) {
                     acc += a.self_val;     // zero unless this is slice 0
                     continue;
@@ -188,7 +371,11 @@ __global__ __launch_bounds__(256) void near_table_kernel(NearArgs a) {
     const double four_pi = 12.566370614359172954;
     const double wm = a.pref / ((double)m * m * m);
     double acc = 0.0;
-    if (d0 | d1 | d2) {
+    if ((d0 | d1 | d2) && a.rule == 1) {
+        const double l = a.l;
+        acc = cell_exact(a.ex, (d0 - 0.5) * l, (d0 + 0.5) * l, (d1 - 0.5) * l, (d1 + 0.5) * l, (d2 - 0.5) * l,
+                         (d2 + 0.5) * l);
+    } else if (d0 | d1 | d2) {
         for (int a0 = 0; a0 < m; ++a0) {
             const int64_t q0 = 2 * m * (int64_t)d0 + (2 * a0 + 1 - m);
             for (int a1 = 0; a1 < m; ++a1) {

@@ -221,6 +221,7 @@ bool is_2a3b(int n) {
 
 struct BoxPlan {
     int n = 0, K = 0, B = 0, m = 1, conserve = 0;
+    int rule = 0;                // mesh kernel: 0 m^3 subpoints, 1 exact cell average
     // ring of slice spectra: lookback slice k is stored in slot (head + k) mod K
     // (lc_advance moves the head back by one, making the oldest slot the newest)
     int head = 0;
@@ -308,7 +309,7 @@ int validate(const lc_plan_desc *d) {
     if (d->use_graph != 0 && d->use_graph != 1) return fail(LC_EINVAL, "use_graph must be 0 or 1");
     for (int b = 0; b < d->n_boxes; ++b) {
         const lc_box_desc &x = d->boxes[b];
-        if (x.reserved != 0) return fail(LC_EINVAL, "box %d: reserved field must be 0", b);
+        if (x.rule != 0 && x.rule != 1) return fail(LC_EINVAL, "box %d: rule must be 0 or 1", b);
         if (x.n < 8 || x.n > 512 || (x.n % 2) || !is_2a3b(x.n) || !supported_n(x.n))
             return fail(LC_EUNSUPPORTED, "box %d: N=%d is not compiled in (even, 2^a 3^b, 8..512)", b, x.n);
         if (x.n_slices < 1 || x.n_slices > 1024)
@@ -326,7 +327,8 @@ int validate(const lc_plan_desc *d) {
             if (!(x.radii[k + 1] > x.radii[k]))
                 return fail(LC_EINVAL, "box %d: radii must be strictly increasing", b);
         const double l = x.box / x.n;
-        if (x.radii[0] == 0.0 && x.radii[1] < 0.5 * std::sqrt(3.0) * l)
+        // (the exact cell average splits the source's own cell between shells)
+        if (x.rule == 0 && x.radii[0] == 0.0 && x.radii[1] < 0.5 * std::sqrt(3.0) * l)
             return fail(LC_EUNSUPPORTED,
                         "box %d: r_1 = %g < (sqrt 3 / 2) l = %g: the self cell would straddle slices", b,
                         x.radii[1], 0.5 * std::sqrt(3.0) * l);
@@ -672,6 +674,7 @@ int lc_plan(const lc_plan_desc *d, lc_plan_t **out) {
         const Layout::BoxOff &o = lay.box[b];
         BoxPlan bp;
         bp.n = x.n; bp.K = x.n_slices; bp.B = x.n_bands; bp.m = x.supersample; bp.conserve = x.conserve;
+        bp.rule = x.rule;
         bp.L = x.box;
         bp.l = x.box / x.n;
         bp.h = x.box / (2.0 * x.supersample * x.n);
@@ -812,6 +815,21 @@ int check_atten(const lc_atten *at, int k) {
 // Kernels of one (box, band), slice k with radial factor A[k] (algorithm
 // steps 2-3). Slices past the last one whose shell meets its factor's
 // support are skipped by the slice sum (kcount).
+// Shell k's constants for the exact cell average (kernel rule 1).
+ExactRule exact_rule(const BoxPlan &bp, const Atten &A, int k) {
+    ExactRule e;
+    e.l = bp.l;
+    e.r_lo = bp.radii[k];
+    e.r_sup = std::min(bp.radii[k + 1], support_end(A));
+    e.pref = A.pref;
+    e.kind = A.kind;
+    e.a = A.a; e.s = A.s; e.p = A.p; e.c = A.c;
+    std::vector<double> x, w;
+    gauss01(16, x, w);
+    for (int j = 0; j < 16; ++j) { e.gx[j] = x[j]; e.gw[j] = w[j]; }
+    return e;
+}
+
 int build_impl(lc_plan_t *p, BoxPlan &bp, int band, const std::vector<Atten> &A) {
     const int n = bp.n, K = bp.K;
     int kc = 0;
@@ -844,6 +862,8 @@ int build_impl(lc_plan_t *p, BoxPlan &bp, int band, const std::vector<Atten> &A)
         a.self_val = (k == 0) ? self : 0.0;
         a.kind = A[k].kind; a.a = A[k].a; a.s = A[k].s; a.p = A[k].p; a.c = A[k].c; a.cut = A[k].cut;
         a.pref = A[k].pref;
+        a.rule = bp.rule;
+        a.ex = exact_rule(bp, A[k], k);
         HIPCHK(launch_greens_build(a, st));
         HIPCHK(launch_x_fwd(n, true, p->scratch_real, true, p->scratch_spec, bp.tw64_half, bp.twist64,
                             nullptr, st));
@@ -1199,6 +1219,8 @@ int lc_near_field(lc_plan_t *p, int32_t box, int32_t band, const lc_sources *src
         a.t_lo = bp.T[k]; a.t_hi = bp.T[k + 1];
         a.r_lo = bp.radii[k]; a.r_hi = bp.radii[k + 1];
         a.kind = A.kind; a.a = A.a; a.s = A.s; a.p = A.p; a.c = A.c; a.cut = A.cut; a.pref = A.pref;
+        a.rule = bp.rule;
+        a.ex = exact_rule(bp, A, k);
         HIPCHK(launch_near_table(a, st));
         HIPCHK(launch_near_corr(a, s.n, (const double *)s.grid, s.lum, s.dtype == LC_F64, st));
     }

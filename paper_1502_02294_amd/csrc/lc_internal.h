@@ -146,6 +146,17 @@ hipError_t launch_col_y_inv_combine(int n, void *spec, const void *tw_full, cons
 
 // Shell kernel builder (FP64): G_k on the octant, mirrored into a full N^3
 // FP64 grid.
+// Exact cell average (kernel rule 1, the m -> infinity limit of the subpoint
+// average) of one shell: pref / l^3 times the integral of phi(r) / (4 pi r^2)
+// over the part of an image cell inside [r_lo, r_sup), r_sup = min(r_{k+1},
+// end of phi's support). gx, gw: 16-point Gauss-Legendre rule on [0, 1].
+struct ExactRule {
+    double l, r_lo, r_sup, pref;
+    int32_t kind;
+    double a, s, p, c;
+    double gx[16], gw[16];
+};
+
 struct BuildArgs {
     double *grid;             // N^3 FP64
     int32_t n, m;
@@ -157,6 +168,8 @@ struct BuildArgs {
     double self_val;          // added at cell 0 when this is slice 0 and self_pair
     int32_t kind;
     double a, s, p, c, cut, pref;
+    int32_t rule;             // 0: m^3 subpoints; 1: exact cell average (ex)
+    ExactRule ex;
 };
 hipError_t launch_greens_build(const BuildArgs &a, hipStream_t st);
 
@@ -178,6 +191,8 @@ struct NearArgs {
     double a, s, p, c, cut, pref;
     double *table;             // (R+1)^3 primary-image mesh kernel of the slice (device)
     double *corr;              // N^3 FP64 correction accumulator (device)
+    int32_t rule;              // mesh kernel rule of the box (BuildArgs::rule)
+    ExactRule ex;
 };
 hipError_t launch_near_table(const NearArgs &a, hipStream_t st);
 hipError_t launch_near_corr(const NearArgs &a, int64_t n_pts, const double *pos, const void *lum, bool lum_f64,

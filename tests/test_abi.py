@@ -42,11 +42,19 @@ def _desc(n=32, box=20.0, K=4, m=1, radii=None, prec=0, ws=0, wsb=0, bands=1, **
     lc = _lc()
     r = radii if radii is not None else [box * 0.9 * k / K for k in range(K + 1)]
     d, keep = lc.make_box_desc(n, box, r, bands, m, kw.get("conserve", 0))
-    for f in ("reserved",):
+    for f in ("rule",):
         if f in kw:
             setattr(d, f, kw[f])
     pd, arr = lc.make_plan_desc([d], prec, 0, ws, wsb, kw.get("use_graph", 0), kw.get("autotune", 0))
     return pd, (keep, arr)
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
 
 
 def _plan_status(pd):
@@ -80,7 +88,7 @@ def test_workspace_bytes_scales_with_problem():
     (dict(radii=[0.0, 5.0, float("nan")]), "LC_EINVAL"),
     (dict(box=-1.0), "LC_EINVAL"),
     (dict(prec=7), "LC_EINVAL"),
-    (dict(reserved=3), "LC_EINVAL"),
+    (dict(rule=3), "LC_EINVAL"),
     (dict(autotune=2), "LC_EINVAL"),
 ])
 def test_invalid_descriptors_rejected_before_device(case, code):
@@ -91,6 +99,24 @@ def test_invalid_descriptors_rejected_before_device(case, code):
     rc, msg = _plan_status(pd2)
     assert lc.STATUS_NAMES[rc] == code, msg
     assert msg and msg != "no error"
+
+
+def test_exact_rule_accepts_a_source_cell_split_between_shells():
+    """r_1 < (sqrt 3 / 2) l splits the source's own cell between slices 0
+    and 1: rejected for the subpoint rule, accepted for the exact cell
+    average (rule 1), which integrates each shell's part of the cell."""
+    lc = _lc()
+    radii = [0.0, 0.1, 5.0]
+    pd0, k0 = _desc(radii=radii)
+    assert lc.lc_workspace_bytes(pd0) == 0
+    pd1, k1 = _desc(radii=radii, rule=1)
+    need = lc.lc_workspace_bytes(pd1)
+    assert need > 0
+    if _has_gpu():
+        pytest.skip("the descriptor's workspace address is a placeholder, not device memory")
+    pd2, k2 = _desc(radii=radii, rule=1, ws=256 * 4096, wsb=need)
+    rc, msg = _plan_status(pd2)
+    assert rc == lc.LC_EDEVICE, msg
 
 
 def test_workspace_checks_then_device():
@@ -106,14 +132,10 @@ def test_workspace_checks_then_device():
     null_ws, k4 = _desc(ws=0, wsb=need)
     rc, msg = _plan_status(null_ws)
     assert rc == lc.LC_EINVAL, msg
-    ok, k5 = _desc(ws=256 * 4096, wsb=need)
-    rc, msg = _plan_status(ok)
-    try:
-        import torch
-        has_gpu = torch.cuda.is_available()
-    except Exception:
-        has_gpu = False
-    if not has_gpu:
+    if not _has_gpu():
+        # (only without a device: the workspace address is a placeholder)
+        ok, k5 = _desc(ws=256 * 4096, wsb=need)
+        rc, msg = _plan_status(ok)
         assert rc == lc.LC_EDEVICE, msg
 
 
@@ -141,7 +163,7 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "lc.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(lc_box_desc), offsetof(lc_box_desc, box), offsetof(lc_box_desc, radii), offsetof(lc_box_desc, reserved));
+  printf("%zu %zu %zu %zu\n", sizeof(lc_box_desc), offsetof(lc_box_desc, box), offsetof(lc_box_desc, radii), offsetof(lc_box_desc, rule));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lc_plan_desc), offsetof(lc_plan_desc, hip_stream), offsetof(lc_plan_desc, workspace_bytes), offsetof(lc_plan_desc, use_graph), offsetof(lc_plan_desc, boxes), offsetof(lc_plan_desc, autotune));
   printf("%zu %zu %zu %zu\n", sizeof(lc_schedule), offsetof(lc_schedule, push_group), offsetof(lc_schedule, n_fused), offsetof(lc_schedule, n_fused_bands));
   printf("%zu %zu %zu\n", sizeof(lc_atten), offsetof(lc_atten, a), offsetof(lc_atten, prefactor));
@@ -158,7 +180,7 @@ int main(void) {
         out = subprocess.check_output([exe], text=True).split("\n")
     b = list(map(int, out[0].split()))
     assert b == [C.sizeof(lc.lc_box_desc), lc.lc_box_desc.box.offset, lc.lc_box_desc.radii.offset,
-                 lc.lc_box_desc.reserved.offset]
+                 lc.lc_box_desc.rule.offset]
     p = list(map(int, out[1].split()))
     assert p == [C.sizeof(lc.lc_plan_desc), lc.lc_plan_desc.hip_stream.offset,
                  lc.lc_plan_desc.workspace_bytes.offset, lc.lc_plan_desc.use_graph.offset,

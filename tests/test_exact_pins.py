@@ -127,3 +127,34 @@ def test_quadrature_order_converged():
             a = oracle.cell_average(at, 1.0, box, r0, r1, ng=24)
             b = oracle.cell_average(at, 1.0, box, r0, r1, ng=48)
             assert abs(a - b) <= 1e-14 * max(1.0, abs(b)), (name, c, r0, r1, a, b)
+
+
+@pytest.mark.parametrize("r_lo,r_hi", [(0.5 + 1e-3, 2.76), (0.5 + 1e-6, 2.6), (2.55, 2.5 + 1e-5 + 0.06),
+                                       (0.3, 2.5 + 1e-7 + 0.2), (2.6, 3.0)])
+def test_near_coincident_breakpoints_vs_mpmath(r_lo, r_hi):
+    """Cells on the z axis, [-1/2, 1/2]^2 x [z0, z1] with z0 > 0, phi = 1, and
+    shell radii just off the cell's edge distances: the integral in R of
+    Theta(R) (2 pi, or 2 pi - 8 acos(1/(2R)) past the edge) times the z
+    integral of R / (R^2 + z^2) (atan differences), to 30 digits by mpmath."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    z0, z1 = mp.mpf(2.5), mp.mpf(3.5)
+    rl, rh = mp.mpf(r_lo), mp.mpf(r_hi)
+
+    def theta(R):
+        return 2 * mp.pi if R <= 0.5 else 2 * mp.pi - 8 * mp.acos(mp.mpf(0.5) / R)
+
+    def V(R):
+        lo = max(z0, mp.sqrt(rl ** 2 - R ** 2)) if rl > R else z0
+        hi = min(z1, mp.sqrt(rh ** 2 - R ** 2)) if rh > R else mp.mpf(0)
+        return mp.atan(hi / R) - mp.atan(lo / R) if hi > lo else mp.mpf(0)
+
+    pts = {mp.mpf(0), mp.mpf(0.5), mp.sqrt(mp.mpf(0.5))}
+    for r in (rl, rh):
+        for z in (z0, z1):
+            if r > z:
+                pts.add(mp.sqrt(r * r - z * z))
+    pts = sorted(p for p in pts if p <= mp.sqrt(mp.mpf(0.5)))
+    ref = mp.quad(lambda R: theta(R) * V(R), pts) / (4 * mp.pi)
+    v = oracle.cell_average(li.Atten(kind=0), 1.0, [-0.5, 0.5, -0.5, 0.5, 2.5, 3.5], r_lo, r_hi)
+    assert abs(v - float(ref)) <= 1e-13 * max(abs(float(ref)), 1e-3), (v, float(ref))
