@@ -393,35 +393,54 @@ def uneven_leg(lc, torch, steps, fp64_steps):
 def rolling_leg(lc, torch, box, grids, steps):
     """The rolling light-cone at the headline shape: per observing time one
     new slice (lc_advance: one forward transform) and the field over all K
-    lookback slices (lc_field: slice sum + one inverse), FP32 form."""
+    lookback slices (lc_field: slice sum + one inverse), FP32 form. Two
+    schedules: the default one, whose fused pass transforms every slice along
+    z at each field, and spectra_3d, which transforms each slice along z once
+    when it is pushed, so that the field is the product and sum alone."""
     n, K = box.n, box.n_slices
-    plan = lc.Plan([box], precision=lc.LC_PREC_FP32, autotune=True)
-    plan.build_all()
-    out = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
-    st = plan.stream
-    with torch.cuda.stream(st):
-        for k in range(K):
-            plan.push_grid(0, k, grids[k])
-        for j in range(3):
-            plan.advance(0, grids[j % K])
-            plan.field(0, 0, out=out)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(st):
-        e0.record(st)
-        for j in range(steps):
-            plan.advance(0, grids[j % K])
-            plan.field(0, 0, out=out)
-        e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    t_fz = plan.time_kernel(lc.LC_KERNEL_FUSED_Z, 0, 3)
-    plan.close()
-    return {"ms_per_observing_step": ms, "cell_slices_per_s": n ** 3 * K / (ms * 1e-3),
-            "fused_z_ms": t_fz,
-            "note": "one lc_advance (1 forward transform) + one lc_field (slice sum over all 40 slices, "
-                    "1 inverse) per observing time, issued eagerly on the plan's stream"}
+    res = {}
+    for mode in ("fused_z", "spectra_3d"):
+        plan = lc.Plan([box], precision=lc.LC_PREC_FP32, autotune=True)
+        plan.build_all()
+        if mode == "spectra_3d":
+            sch = plan.get_schedule(0)
+            # the fastest whole-plane xy shape (3D spectra need one)
+            best = None
+            for v in range(sch["n_xy"]):
+                try:
+                    plan.set_schedule(0, xy_variant=v, spectra_3d=1)
+                except lc.LCError:
+                    continue
+                t = plan.time_kernel(lc.LC_KERNEL_XY_FWD, 0, 3)
+                if best is None or t < best[0]:
+                    best = (t, v)
+            plan.set_schedule(0, xy_variant=best[1], spectra_3d=1)
+        out = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
+        st = plan.stream
+        with torch.cuda.stream(st):
+            for k in range(K):
+                plan.push_grid(0, k, grids[k])
+            for j in range(3):
+                plan.advance(0, grids[j % K])
+                plan.field(0, 0, out=out)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(st):
+            e0.record(st)
+            for j in range(steps):
+                plan.advance(0, grids[j % K])
+                plan.field(0, 0, out=out)
+            e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        t_fz = plan.time_kernel(lc.LC_KERNEL_FUSED_Z, 0, 3)
+        res[mode] = {"ms_per_observing_step": ms, "cell_slices_per_s": n ** 3 * K / (ms * 1e-3),
+                     "fused_z_ms": t_fz, "schedule": plan.get_schedule(0)}
+        plan.close()
+    res["note"] = ("one lc_advance (1 forward transform) + one lc_field (slice sum over all 40 slices, "
+                   "1 inverse) per observing time, issued eagerly on the plan's stream")
+    return res
 
 
 def main():
@@ -470,6 +489,11 @@ def main():
             line["grid512_bands4"] = bands_leg(lc, torch, max(3, args.steps // 4), 0 if args.no_fp64 else 2)
         if "uneven16" in extras:
             line["uneven16"] = uneven_leg(lc, torch, max(5, args.steps // 2), 0 if args.no_fp64 else 3)
+        if "rolling" in extras:
+            w, _ = workload(args.workload)
+            box = w.boxes[0]
+            g32 = [torch.from_numpy(li.dense_grid(box.n, c, v).astype(np.float32)).cuda() for c, v in box.sources]
+            line["rolling"] = rolling_leg(lc, torch, box, g32, max(10, args.steps))
         print(json.dumps(line), flush=True)
         return
     w, desc = workload(args.workload)
@@ -554,7 +578,8 @@ def main():
     if "rolling" in extras:
         log("rolling light-cone leg")
         line["rolling"] = rolling_leg(lc, torch, box, g32, max(10, args.steps))
-        log(f"rolling {line['rolling']['ms_per_observing_step']:.3f} ms/observing step")
+        log("rolling " + ", ".join(f"{m} {line['rolling'][m]['ms_per_observing_step']:.3f}"
+                                    for m in ("fused_z", "spectra_3d")) + " ms/observing step")
     del g32, out32, out64
     torch.cuda.empty_cache()
     if "grid512_bands4" in extras:

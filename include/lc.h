@@ -386,14 +386,23 @@ typedef enum {
  *                  in the other forms). With 1 or 2 the sum over slices is
  *                  compensated (Kahan); with 3 or 4 (N = 384, 512) it is a
  *                  plain FP32 sum. Default n_fused_bands; not tuned.
+ *   spectra_3d     1: the slice spectra are stored transformed along z as
+ *                  well (3D spectra, as in the plain forms): each push adds
+ *                  the z pass, and a field is the product with G^ and the
+ *                  sum over slices alone, then one inverse per band (the
+ *                  regime of a rolling light-cone, where each observing
+ *                  time pushes one slice and sums all K). Needs a
+ *                  whole-plane xy shape. 0 (default): the fused z pass
+ *                  transforms every slice along z at each field. FP32 form
+ *                  only (-1 in the other forms); not tuned
  *   n_xy, n_fused, n_fused_bands  (lc_get_schedule only) shapes compiled
  *                  for this N/form; n_fused_bands = min(B, 4 at N = 384,
  *                  512, else 2)
  * lc_set_schedule validates every field (LC_EINVAL) and applies them to
  * later launches; the next lc_step captures a new graph. Changing whether
- * the fused xy pass is used, or between whole-plane and parity-layout
- * shapes, clears the box's pushed slices (they read as zero until pushed
- * again). FP64 input grids (and point lists) use the first shape of the
+ * the fused xy pass is used, between whole-plane and parity-layout shapes,
+ * or spectra_3d, clears the box's pushed slices (they read as zero until
+ * pushed again). FP64 input grids (and point lists) use the first shape of the
  * same layout (0 or 4). */
 typedef struct {
     int32_t xy_variant;
@@ -404,6 +413,7 @@ typedef struct {
     int32_t n_fused;
     int32_t fused_bands;
     int32_t n_fused_bands;
+    int32_t spectra_3d;
 } lc_schedule;
 
 int lc_get_schedule(lc_plan_t *plan, int32_t box, lc_schedule *out);

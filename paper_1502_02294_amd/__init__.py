@@ -54,7 +54,7 @@ class lc_plan_desc(C.Structure):
 class lc_schedule(C.Structure):
     _fields_ = [("xy_variant", C.c_int32), ("fused_variant", C.c_int32), ("fused_rounds", C.c_int32),
                 ("push_group", C.c_int32), ("n_xy", C.c_int32), ("n_fused", C.c_int32),
-                ("fused_bands", C.c_int32), ("n_fused_bands", C.c_int32)]
+                ("fused_bands", C.c_int32), ("n_fused_bands", C.c_int32), ("spectra_3d", C.c_int32)]
 
 
 class lc_atten(C.Structure):

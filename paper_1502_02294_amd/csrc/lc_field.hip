@@ -141,9 +141,13 @@ __device__ __forceinline__ int64_t fused_slot_tile(int64_t slot, int64_t main_ti
 // input element is read once for both, and both go through the z transform,
 // the kernel product and the compensated sum. Output o of a column is at
 // o * (N/2 rows) after the first; a second part goes to part slot 2 w + o.
-template <int L, int NB_, typename S, int PF, bool PAR>
+template <int L, int NB_, typename S, int PF, int IN>
 __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDev a, ColSet s0, ColSet s1,
                                                                         const cx<float> *__restrict__ tw_g) {
+    // input: 0 y-transformed slices, 1 the same in the parity layout, 2
+    // slices already transformed along z as well (3D spectra: no forward z
+    // transform here, the slice loop is the product and the sum)
+    constexpr bool PAR = IN == 1, PRE = IN == 2;
     using SH = FusedShape<L, S>;
     using EF = Engine<float, L, true, S>;     // forward z transform
     using EI = Engine<float, L, false, S>;    // inverse z transform
@@ -247,10 +251,12 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // column: uniform deltas too, except the last row, which is clamped
         // for the threads past the octant's end). One offset register each
         // instead of one per element.
-        const uint32_t xoff0 = (uint32_t)((cbase + (int64_t)EF::in_pos(t, 0) * s.row_stride) * 8);
+        // (3D spectra are read at the forward transform's output positions)
+        auto rowpos = [&](int e) { return PRE ? EF::out_pos(t, e) : EF::in_pos(t, e); };
+        const uint32_t xoff0 = (uint32_t)((cbase + (int64_t)rowpos(0) * s.row_stride) * 8);
         const int64_t rs8 = s.row_stride * 8;
         auto xld = [&](const char *base, int e) {
-            return *(const cx<float> *)(base + (int64_t)(EF::in_pos(t, e) - EF::in_pos(t, 0)) * rs8 + xoff0);
+            return *(const cx<float> *)(base + (int64_t)(rowpos(e) - rowpos(0)) * rs8 + xoff0);
         };
         constexpr bool GFULL = GROWS * RSTEP <= HP;   // every thread's last row exists
         const int rlast = t + (GROWS - 1) * RSTEP;
@@ -382,6 +388,26 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
                             load_g(k + 1);
                         },
                         [&](int o, const cx<float>(&v)[E]) { mac(o, &gl[0][0][0], v); });
+                }
+            }
+        } else if constexpr (PRE) {
+            store_g(k0);
+            for (int kk = k0; kk < kend; kk += PF) {
+#pragma unroll
+                for (int j = 0; j < PF; ++j) {
+                    const int k = kk + j;
+                    const float *glk = &gl[k & 1][0][0];
+                    load_g(k + 1);
+                    // slice k's octant rows (stored at the end of slice k - 1)
+                    // are visible, and every reader of slice k - 1's rows is
+                    // done before they are overwritten at the end of this slice
+                    lds_barrier();
+                    cx<float> v[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] = xb[j][e];
+                    fill(j, k + PF);
+                    mac(0, glk, v);
+                    store_g(k + 1);
                 }
             }
         } else {
@@ -649,14 +675,14 @@ template <int N> struct HasSched8 {
     static constexpr bool value = (N == 64 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512);
 };
 
-template <int N, int NB, typename S, int PF, bool PAR>
+template <int N, int NB, typename S, int PF, int IN>
 static int fused_slots() {
     static int cached = 0;
     if (cached) return cached;
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S, PF, PAR>, FusedShape<N, S>::NT,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_z_kernel<N, NB, S, PF, IN>, FusedShape<N, S>::NT,
                                                      0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -667,18 +693,19 @@ static int fused_slots() {
 // Three or four bands per launch (plain sums, prefetch depth 1): compiled
 // at N = 384 and 512, where the slice spectra are the largest and reading
 // them once for four bands instead of twice pays most.
-template <int N, int PF, bool PAR> constexpr bool fused_nb4() { return (N == 384 || N == 512) && PF == 1 && !PAR; }
+template <int N, int PF, int IN> constexpr bool fused_nb4() { return (N == 384 || N == 512) && PF == 1 && IN != 1; }
 
-template <int N, typename S, int PF, bool PAR>
+template <int N, typename S, int PF, int IN>
 static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                                int64_t tiles, int kmax) {
     static_assert(FusedShape<N, S>::CPW == FusedShape<N, FusedTiling<N>>::CPW, "variants share the tiling");
+    constexpr bool PAR = IN == 1;
     int slots = 0;
     if (fa.nband > 2) {
-        if constexpr (fused_nb4<N, PF, PAR>()) slots = fused_slots<N, 4, S, PF, PAR>();
+        if constexpr (fused_nb4<N, PF, IN>()) slots = fused_slots<N, 4, S, PF, IN>();
         else return hipErrorInvalidValue;
     } else {
-        slots = fa.nband == 2 ? fused_slots<N, 2, S, PF, PAR>() : fused_slots<N, 1, S, PF, PAR>();
+        slots = fa.nband == 2 ? fused_slots<N, 2, S, PF, IN>() : fused_slots<N, 1, S, PF, IN>();
     }
     // (two part slots per workgroup with two outputs per tile)
     const int64_t P = std::min<int64_t>(std::min<int64_t>(slots, tiles), fa.max_parts / (PAR ? 2 : 1));
@@ -700,14 +727,14 @@ static hipError_t fused_launch(const FusedArgs &fa, const void *tw, hipStream_t 
                            (int *)fa.split_tab, tiles, (int64_t)kmax, P, d.W, PAR ? 1 : 0, (int64_t)s0.n_wgs);
     constexpr int NT = FusedShape<N, S>::NT;
     if (fa.nband > 2) {
-        if constexpr (fused_nb4<N, PF, PAR>())
-            hipLaunchKernelGGL((fused_z_kernel<N, 4, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        if constexpr (fused_nb4<N, PF, IN>())
+            hipLaunchKernelGGL((fused_z_kernel<N, 4, S, PF, IN>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                                (const cx<float> *)tw);
     } else if (fa.nband == 2)
-        hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 2, S, PF, IN>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     else
-        hipLaunchKernelGGL((fused_z_kernel<N, 1, S, PF, PAR>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
+        hipLaunchKernelGGL((fused_z_kernel<N, 1, S, PF, IN>), dim3((unsigned)P), dim3(NT), 0, st, d, s0, s1,
                            (const cx<float> *)tw);
     const int64_t full = tiles / P * P;
     if (fa.rounds && full < tiles) {
@@ -733,7 +760,7 @@ template <int N> constexpr bool fused_par() { return N == 192 || N == 256; }
 static_assert((256 / 2) % FusedShape<256, FusedTiling<256>>::CPW == 0, "pair tiles cover whole rows");
 static_assert((192 / 2) % FusedShape<192, FusedTiling<192>>::CPW == 0, "pair tiles cover whole rows");
 
-template <int N, bool PAR>
+template <int N, int IN>
 static hipError_t fused_sched(const FusedArgs &fa, const void *tw, hipStream_t st, ColSet s0, ColSet s1,
                               int64_t tiles, int kmax) {
     // variant = 2 * schedule + (prefetch depth 1 ? 1 : 0); schedule 1 = Sched8
@@ -742,24 +769,25 @@ static hipError_t fused_sched(const FusedArgs &fa, const void *tw, hipStream_t s
     const int sched = fused_sched8_only<N>() ? 1 : fa.variant / 2, pf = fa.variant % 2 || fa.nband > 2 ? 1 : 2;
     if constexpr (HasSched8<N>::value) {
         if (sched == 1)
-            return pf == 1 ? fused_launch<N, Sched8<N>, 1, PAR>(fa, tw, st, s0, s1, tiles, kmax)
-                           : fused_launch<N, Sched8<N>, 2, PAR>(fa, tw, st, s0, s1, tiles, kmax);
+            return pf == 1 ? fused_launch<N, Sched8<N>, 1, IN>(fa, tw, st, s0, s1, tiles, kmax)
+                           : fused_launch<N, Sched8<N>, 2, IN>(fa, tw, st, s0, s1, tiles, kmax);
     }
     if constexpr (!fused_sched8_only<N>()) {
-        return pf == 1 ? fused_launch<N, Sched<N>, 1, PAR>(fa, tw, st, s0, s1, tiles, kmax)
-                       : fused_launch<N, Sched<N>, 2, PAR>(fa, tw, st, s0, s1, tiles, kmax);
+        return pf == 1 ? fused_launch<N, Sched<N>, 1, IN>(fa, tw, st, s0, s1, tiles, kmax)
+                       : fused_launch<N, Sched<N>, 2, IN>(fa, tw, st, s0, s1, tiles, kmax);
     }
     return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
-    if (fa.parity && !fused_par<N>()) return hipErrorInvalidValue;
+    if (fa.parity && (fa.pre || !fused_par<N>())) return hipErrorInvalidValue;
     ColSet s0, s1;
     fused_sets<N>(s0, s1, fa.parity != 0);
     const int64_t tiles = s0.n_wgs + s1.n_wgs;
     const int64_t std_tiles = fa.parity ? 2 * tiles : tiles;
-    const int kmax = std::max(fa.kcount[0], fa.nband > 1 ? fa.kcount[1] : 0);
+    int kmax = 0;
+    for (int b = 0; b < fa.nband; ++b) kmax = std::max(kmax, fa.kcount[b]);
     if (kmax <= 0) {
         // no slice contributes: the accumulators are zero (and so are the
         // kernels' DC values, hence the means)
@@ -778,9 +806,10 @@ static hipError_t fused_t(const FusedArgs &fa, const void *tw, hipStream_t st) {
         return hipGetLastError();
     }
     if constexpr (fused_par<N>()) {
-        if (fa.parity) return fused_sched<N, true>(fa, tw, st, s0, s1, tiles, kmax);
+        if (fa.parity) return fused_sched<N, 1>(fa, tw, st, s0, s1, tiles, kmax);
     }
-    return fused_sched<N, false>(fa, tw, st, s0, s1, tiles, kmax);
+    if (fa.pre) return fused_sched<N, 2>(fa, tw, st, s0, s1, tiles, kmax);
+    return fused_sched<N, 0>(fa, tw, st, s0, s1, tiles, kmax);
 }
 
 // variants: bit 0 selects a prefetch depth of 1 (else 2) slices (fewer

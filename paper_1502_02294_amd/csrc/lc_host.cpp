@@ -245,6 +245,9 @@ struct BoxPlan {
     int64_t max_parts = 0, part_stride = 0, tiles = 0;
     int fused_variant = 0, fused_rounds = 1;
     int fused_bands = 1;         // bands per fused z launch (3-4: plain sums)
+    // FP32 form: slice spectra stored transformed along z too (3D), so that a
+    // field is the product and sum alone; every push adds the z pass
+    bool spec3d = false;
     int xy_variant = 0;          // launch shape of the fused xy pass
     int push_group = 2;          // slices per batched forward launch in lc_step
     unsigned long long *maxima = nullptr;
@@ -488,6 +491,7 @@ FusedArgs fused_args(const BoxPlan &bp) {
     fa.variant = bp.fused_variant;
     fa.rounds = bp.fused_rounds;
     fa.parity = bp.parity() ? 1 : 0;
+    fa.pre = bp.spec3d ? 1 : 0;
     return fa;
 }
 
@@ -988,7 +992,7 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
         HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, spec, bp.tw_half, bp.twist, dcp, st));
         HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
     }
-    if (p->prec != LC_PREC_FP32) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
+    if (p->prec != LC_PREC_FP32 || bp.spec3d) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
     bp.pushed[slot] = 1;
     return LC_OK;
 }
@@ -1053,6 +1057,7 @@ static int field_box(lc_plan_t *p, int box, int b0, int b1, void *const *outp, b
             fa.split_tab = tab;
             fa.zero_dc = 1; fa.kahan = nb <= 2; fa.variant = bp.fused_variant; fa.rounds = bp.fused_rounds;
             fa.parity = bp.parity() ? 1 : 0;
+            fa.pre = bp.spec3d ? 1 : 0;
             fa.ring = bp.head;
             fa.frozen = frozen;
             fa.sk = bp.sk; fa.g0 = bp.ghat0; fa.inv_n3 = inv_n3; fa.mu = bp.mu;
@@ -1277,7 +1282,8 @@ static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *ou
                                       dcp, st));
             HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, st));
         }
-        if (p->prec != LC_PREC_FP32) HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
+        if (p->prec != LC_PREC_FP32 || bp.spec3d)
+            HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
         for (int j = 0; j < cnt; ++j) bp.pushed[slot0 + j] = 1;
         k += cnt;
     }
@@ -1512,6 +1518,7 @@ int lc_get_schedule(lc_plan_t *p, int32_t box, lc_schedule *out) {
     out->push_group = bp.push_group;
     out->fused_bands = fused ? bp.fused_bands : -1;
     out->n_fused_bands = fused ? std::min(bp.B, fused_max_bands(bp.n)) : 0;
+    out->spectra_3d = fused ? (bp.spec3d ? 1 : 0) : -1;
     return ok();
 }
 
@@ -1531,9 +1538,15 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     const int max_bands = fused ? std::min(bp.B, fused_max_bands(bp.n)) : 0;
     if (fused ? (s->fused_bands < 1 || s->fused_bands > max_bands) : s->fused_bands != -1)
         return fail(LC_EINVAL, "fused_bands %d not available (1..%d)", s->fused_bands, max_bands);
+    if (fused ? (s->spectra_3d != 0 && s->spectra_3d != 1) : s->spectra_3d != -1)
+        return fail(LC_EINVAL, "spectra_3d must be 0 or 1 (FP32 form), -1 otherwise");
+    if (s->spectra_3d == 1 && s->xy_variant >= 0 && xy_parity(bp.n, s->xy_variant))
+        return fail(LC_EINVAL, "spectra_3d needs a whole-plane xy shape (xy_variant %d is a parity-layout shape)",
+                    s->xy_variant);
     const bool use_xy = s->xy_variant >= 0;
     const bool par = use_xy && xy_parity(bp.n, s->xy_variant);
-    if (use_xy != bp.use_xy || par != bp.parity()) {
+    const bool s3 = fused && s->spectra_3d == 1;
+    if (use_xy != bp.use_xy || par != bp.parity() || s3 != bp.spec3d) {
         // the spectrum and DC partial layouts change with the forward pass:
         // pushed slices are dropped
         const size_t cs = p->t_f64 ? 16 : 8;
@@ -1548,6 +1561,7 @@ int lc_set_schedule(lc_plan_t *p, int32_t box, const lc_schedule *s) {
     if (fused) {
         bp.fused_variant = s->fused_variant;
         bp.fused_bands = s->fused_bands;
+        bp.spec3d = s3;
     }
     bp.fused_rounds = s->fused_rounds;
     bp.push_group = s->push_group;

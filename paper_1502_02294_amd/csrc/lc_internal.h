@@ -123,6 +123,7 @@ struct FusedArgs {
     int32_t variant;         // register schedule: 0 default, 1 eight elements per thread
     int32_t rounds;          // 1: whole tiles in rounds instead of the balanced split
     int32_t parity;          // 1: spectra in the parity y layout of the half-plane xy shapes
+    int32_t pre = 0;         // 1: spectra already transformed along z (3D): product and sum only
     int32_t ring = 0;        // lookback slice k is stored in spectrum slot (k + ring) mod K
     int32_t frozen = -1;     // >= 0: every lookback slice reads spectrum slot `frozen`
     // band means mu[band0 + j] = inv_n3 * sum_k g0[k B + band0 + j] sk[k] (the FP64

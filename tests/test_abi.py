@@ -165,7 +165,7 @@ def test_struct_layouts_match_header():
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(lc_box_desc), offsetof(lc_box_desc, box), offsetof(lc_box_desc, radii), offsetof(lc_box_desc, rule));
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(lc_plan_desc), offsetof(lc_plan_desc, hip_stream), offsetof(lc_plan_desc, workspace_bytes), offsetof(lc_plan_desc, use_graph), offsetof(lc_plan_desc, boxes), offsetof(lc_plan_desc, autotune));
-  printf("%zu %zu %zu %zu\n", sizeof(lc_schedule), offsetof(lc_schedule, push_group), offsetof(lc_schedule, n_fused), offsetof(lc_schedule, n_fused_bands));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(lc_schedule), offsetof(lc_schedule, push_group), offsetof(lc_schedule, n_fused), offsetof(lc_schedule, n_fused_bands), offsetof(lc_schedule, spectra_3d));
   printf("%zu %zu %zu\n", sizeof(lc_atten), offsetof(lc_atten, a), offsetof(lc_atten, prefactor));
   printf("%zu %zu %zu %zu\n", sizeof(lc_sources), offsetof(lc_sources, grid), offsetof(lc_sources, n), offsetof(lc_sources, lum));
   return 0;
@@ -187,7 +187,7 @@ int main(void) {
                  lc.lc_plan_desc.boxes.offset, lc.lc_plan_desc.autotune.offset]
     sc = list(map(int, out[2].split()))
     assert sc == [C.sizeof(lc.lc_schedule), lc.lc_schedule.push_group.offset, lc.lc_schedule.n_fused.offset,
-                  lc.lc_schedule.n_fused_bands.offset]
+                  lc.lc_schedule.n_fused_bands.offset, lc.lc_schedule.spectra_3d.offset]
     a = list(map(int, out[3].split()))
     assert a == [C.sizeof(lc.lc_atten), lc.lc_atten.a.offset, lc.lc_atten.prefactor.offset]
     s = list(map(int, out[4].split()))

@@ -32,14 +32,18 @@ def _box(n, K, bands, seed):
     return li.Box(n=n, box=L, radii=radii, supersample=2, bands=bands, sources=srcs)
 
 
-@pytest.mark.parametrize("nbands", [4, 3])
-def test_bands_per_fused_launch_384(nbands):
+@pytest.mark.parametrize("nbands,order", [(4, "falling"), (3, "falling"), (4, "rising")])
+def test_bands_per_fused_launch_384(nbands, order):
     lc = _lc()
     n, K = 384, 4
     L = 0.78125 * n
     # horizons inside the lookback range: the later bands carry fewer slices
+    # ("rising": the last band of a launch reaches the most slices, so the
+    # launch's slice count must come from every band, not the first two)
     horizons = [0.44 * L, 0.3 * L, 0.2 * L, 0.12 * L][:nbands]
-    box = _box(n, K, [li.lw_band(h) for h in horizons], seed=41 + nbands)
+    if order == "rising":
+        horizons = horizons[::-1]
+    box = _box(n, K, [li.lw_band(h) for h in horizons], seed=41 + nbands + (order == "rising"))
     tg = li.sample_cells([9, n], n, 2000)
     Jr = [oracle.field_direct_ondemand(n, L, box.radii, box.supersample, at, box.sources, tg)
           for at in box.bands]
@@ -53,7 +57,7 @@ def test_bands_per_fused_launch_384(nbands):
     ref2 = None
     for fb in (2, nbands, 1):
         for r in (1, 0):
-            print(f"case n={n} nbands={nbands} fused_bands={fb} rounds={r}", flush=True)
+            print(f"case n={n} nbands={nbands} {order} fused_bands={fb} rounds={r}", flush=True)
             plan.set_schedule(0, fused_bands=fb, fused_rounds=r)
             Js = [plan.field(0, b).double().cpu().numpy().ravel() for b in range(nbands)]
             for b in range(nbands):

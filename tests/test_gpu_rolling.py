@@ -88,6 +88,89 @@ def test_rolling_matches_oracle_and_fresh_plan(form, as_points):
     roll.close()
 
 
+@pytest.mark.parametrize("n,bands", [(32, 1), (48, 2), (128, 1)])
+def test_rolling_with_3d_spectra(n, bands):
+    """spectra_3d = 1: every push (lc_push_sources, lc_advance, lc_step)
+    also transforms the slice along z, and a field is the product with G^
+    and the sum over slices alone. Four observing times against the oracle
+    and against the default schedule (which transforms along z in the
+    fused pass: equal up to FP32 rounding), and lc_step at the last ring
+    position against lc_field."""
+    lc = _lc()
+    K, steps = 5, 4
+    L = 0.9 * n
+    radii = np.linspace(0.0, 0.85 * L, K + 1)
+    bins = _bins(n, K + steps, 55 + n)
+    ats = [li.lw_band(0.8 * L), li.Atten(kind=0)][:bands]
+    box = li.Box(n=n, box=L, radii=radii, supersample=2, bands=ats, sources=_lookback(bins, K, 0))
+    tg = np.arange(n ** 3) if n <= 48 else li.sample_cells([3, n], n, 2000)
+    Gs = [oracle.build_G(n, L, radii, 2, at) for at in ats] if n <= 48 else None
+    plans = {}
+    for s3 in (0, 1):
+        p = lc.Plan([box], precision=lc.LC_PREC_FP32)
+        p.build_all()
+        if s3:
+            sch = p.get_schedule(0)
+            xv = sch["xy_variant"]
+            if xv >= 0 and xv >= {192: 2, 256: 4}.get(n, 99):
+                xv = 0
+            p.set_schedule(0, spectra_3d=1, xy_variant=xv)
+            assert p.get_schedule(0)["spectra_3d"] == 1
+        plans[s3] = p
+    grids = [torch.from_numpy(li.dense_grid(n, c, v)).float().cuda() for c, v in bins]
+    keep = []
+    for s3, p in plans.items():
+        for k in range(K):
+            keep.append(p.push_grid(0, k, grids[K - 1 - k]))
+    for t in range(steps):
+        srcs = _lookback(bins, K, t)
+        for s3, p in plans.items():
+            if t > 0:
+                p.advance(0, grids[t + K - 1])
+        for b, at in enumerate(ats):
+            J3 = plans[1].field(0, b).double().cpu().numpy().ravel()
+            J0 = plans[0].field(0, b).double().cpu().numpy().ravel()
+            if Gs is not None:
+                Jr = oracle.field_direct(Gs[b], srcs, tg)
+            else:
+                Jr = oracle.field_direct_ondemand(n, L, radii, 2, at, srcs, tg)
+            e_max, e_rms = oracle.rel_errors(J3[tg], Jr)
+            d = np.sqrt(np.mean((J3 - J0) ** 2) / np.mean(J0 ** 2))
+            say(f"rolling 3d n={n} t={t} band={b}: e_max={e_max:.3e} e_rms={e_rms:.3e} vs default {d:.3e}")
+            assert e_rms <= 1e-5 and e_max <= 1e-4
+            assert d <= 1e-6
+    # a whole step at the last ring position equals the eager field
+    out = [torch.empty((n,) * 3, dtype=torch.float32, device="cuda") for _ in ats]
+    t = steps - 1
+    plans[1].step([grids[t + K - 1 - k] for k in range(K)], out)
+    for b in range(bands):
+        Jf = plans[1].field(0, b)
+        torch.cuda.synchronize()
+        assert torch.equal(out[b], Jf)
+    for p in plans.values():
+        p.close()
+
+
+def test_spectra_3d_schedule_checks():
+    lc = _lc()
+    n, K = 256, 2
+    box = li.Box(n=n, box=200.0, radii=np.linspace(0.0, 20.0, K + 1), supersample=1, bands=[li.Atten()],
+                 sources=_bins(n, K, 5))
+    p = lc.Plan([box], precision=lc.LC_PREC_FP32)
+    for bad in (dict(spectra_3d=2), dict(spectra_3d=1, xy_variant=4), dict(spectra_3d=-1)):
+        with pytest.raises(lc.LCError) as ei:
+            p.set_schedule(0, **bad)
+        assert ei.value.code == lc.LC_EINVAL
+    p.set_schedule(0, spectra_3d=1, xy_variant=1)
+    assert p.get_schedule(0)["spectra_3d"] == 1
+    p.close()
+    p64 = lc.Plan([box], precision=lc.LC_PREC_FP64)
+    assert p64.get_schedule(0)["spectra_3d"] == -1
+    with pytest.raises(lc.LCError):
+        p64.set_schedule(0, spectra_3d=1)
+    p64.close()
+
+
 def test_rolling_step_after_advance_parity_layout():
     """256^3 with the autotuned (parity layout) shapes: lc_step captures a
     graph for the current ring position; after lc_advance the next lc_step
