@@ -159,10 +159,16 @@ __device__ __forceinline__ void col_lane(bool rowfast, int &c, int &t) {
     else { c = threadIdx.x % CPW; t = threadIdx.x / CPW; }
 }
 
-template <typename T, int L, bool FWD, bool COMBINE>
+// TILED (z forward into the slice-sum pass's tile order): the transformed
+// columns go to `out`, each set (main, nyq) as consecutive tiles of tcpw
+// columns (the last one narrower), a tile's rows contiguous:
+//   element (row r, column col) at set_off + c0 L + r w + (col - c0),
+//   c0 = col - col mod tcpw, w = min(tcpw, n_cols - c0).
+template <typename T, int L, bool FWD, bool COMBINE, bool TILED = false>
 __global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(
     cx<T> *data0, int64_t data_stride, ColSet s0, ColSet s1, const cx<T> *__restrict__ tw_g,
-    const int *__restrict__ tab, const cx<T> *__restrict__ part, int64_t tiles_main, int cpw_z) {
+    const int *__restrict__ tab, const cx<T> *__restrict__ part, int64_t tiles_main, int cpw_z,
+    cx<T> *__restrict__ out = nullptr, int tcpw = 1) {
     // workgroup blockIdx.x handles tile (blockIdx.x % per) of spectrum (blockIdx.x / per)
     const int per = s0.n_wgs + s1.n_wgs;
     const int bid = blockIdx.x % per;
@@ -204,7 +210,15 @@ __global__ __launch_bounds__((ColShape<T, L>::NT)) void col_kernel(
         }
     }
     EN::run(x, lds, c, ES, t, tws);
-    if (ok) {
+    if constexpr (TILED) {
+        if (ok) {
+            const int64_t c0 = col - col % tcpw;
+            const int64_t w = s.n_cols - c0 < tcpw ? s.n_cols - c0 : tcpw;
+            cx<T> *o = out + (first ? 0 : spec_main(L)) + c0 * L + (col - c0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) o[EN::out_pos(t, e) * w] = x[e];
+        }
+    } else if (ok) {
 #pragma unroll
         for (int e = 0; e < E; ++e) data[base + EN::out_pos(t, e) * s.row_stride] = x[e];
     }
@@ -353,6 +367,26 @@ static hipError_t col_t(int axis, bool fwd, void *spec, int64_t stride, int coun
         hipLaunchKernelGGL((col_kernel<T, N, false, false>), grid, dim3(SH::NT), 0, st, (cx<T> *)spec, stride,
                            s0, s1, (const cx<T> *)tw, nullptr, nullptr, (int64_t)0, 1);
     return hipGetLastError();
+}
+
+// z forward of one FP32 spectrum into the tile order of the slice-sum pass
+template <int N>
+static hipError_t col_z_tiled_t(const void *in, void *out, const void *tw, hipStream_t st) {
+    using SH = ColShape<float, N>;
+    ColSet s0, s1;
+    col_sets<float, N>(2, s0, s1);
+    hipLaunchKernelGGL((col_kernel<float, N, true, false, true>), dim3(s0.n_wgs + s1.n_wgs), dim3(SH::NT), 0, st,
+                       (cx<float> *)in, (int64_t)0, s0, s1, (const cx<float> *)tw, nullptr, nullptr, (int64_t)0, 1,
+                       (cx<float> *)out, fused_cpw(N));
+    return hipGetLastError();
+}
+
+hipError_t launch_col_z_tiled(int n, const void *in, void *out, const void *tw_full, hipStream_t st) {
+    if (in == out) return hipErrorInvalidValue;
+#define X_(N) return col_z_tiled_t<N>(in, out, tw_full, st)
+    LC_DISPATCH_N(n, X_);
+#undef X_
+    return hipSuccess;
 }
 
 template <int N>

@@ -251,10 +251,18 @@ __global__ __launch_bounds__((FusedShape<L, S>::NT)) void fused_z_kernel(FusedDe
         // column: uniform deltas too, except the last row, which is clamped
         // for the threads past the octant's end). One offset register each
         // instead of one per element.
-        // (3D spectra are read at the forward transform's output positions)
+        // (3D spectra are read at the forward transform's output positions,
+        // from the tile order their z pass writes: the tile's rows of w
+        // columns contiguous, w = CPW except in a set's last tile)
         auto rowpos = [&](int e) { return PRE ? EF::out_pos(t, e) : EF::in_pos(t, e); };
-        const uint32_t xoff0 = (uint32_t)((cbase + (int64_t)rowpos(0) * s.row_stride) * 8);
-        const int64_t rs8 = s.row_stride * 8;
+        int64_t in0 = cbase, in_rs = s.row_stride;
+        if constexpr (PRE) {
+            const int64_t w = s.n_cols - col0 < CPW ? s.n_cols - col0 : CPW;
+            in0 = (is_main ? 0 : spec_main(L)) + col0 * L + (ccol - col0);
+            in_rs = w;
+        }
+        const uint32_t xoff0 = (uint32_t)((in0 + (int64_t)rowpos(0) * in_rs) * 8);
+        const int64_t rs8 = in_rs * 8;
         auto xld = [&](const char *base, int e) {
             return *(const cx<float> *)(base + (int64_t)(rowpos(e) - rowpos(0)) * rs8 + xoff0);
         };

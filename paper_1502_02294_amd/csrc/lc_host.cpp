@@ -983,16 +983,22 @@ static int push_impl(lc_plan_t *p, int box, int slice, const lc_sources *s) {
     char *spec = bp.spec + (size_t)slot * spec_elems(n) * cs;
     // FP64 input sums (the FP32 form's FP64 mean and its non-finite check)
     double *dcp = p->prec == LC_PREC_FP32 ? bp.dcpart + (size_t)slot * bp.dcw : nullptr;
+    // 3D spectra (FP32 form): the x and y passes write the plan's staging
+    // spectrum, from which the z pass writes the slot in the slice-sum pass's
+    // tile order
+    const bool s3 = p->prec == LC_PREC_FP32 && bp.spec3d;
+    char *fwd = s3 ? p->scratch_spec : spec;
     if (bp.use_xy) {
         SrcTab tab;
         tab.p[0] = in;
-        HIPCHK(launch_xy_fwd_batch(n, tab, 1, in_f64, spec, 0, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.dcw,
+        HIPCHK(launch_xy_fwd_batch(n, tab, 1, in_f64, fwd, 0, bp.tw_half, bp.twist, bp.tw_full, dcp, bp.dcw,
                                    bp.xy_variant, st));
     } else {
-        HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, spec, bp.tw_half, bp.twist, dcp, st));
-        HIPCHK(launch_col(n, p->t_f64, 1, true, spec, bp.tw_full, st));
+        HIPCHK(launch_x_fwd(n, p->t_f64, in, in_f64, fwd, bp.tw_half, bp.twist, dcp, st));
+        HIPCHK(launch_col(n, p->t_f64, 1, true, fwd, bp.tw_full, st));
     }
-    if (p->prec != LC_PREC_FP32 || bp.spec3d) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
+    if (p->prec != LC_PREC_FP32) HIPCHK(launch_col(n, p->t_f64, 2, true, spec, bp.tw_full, st));
+    if (s3) HIPCHK(launch_col_z_tiled(n, fwd, spec, bp.tw_full, st));
     bp.pushed[slot] = 1;
     return LC_OK;
 }
@@ -1255,7 +1261,8 @@ static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *ou
     int k = 0;
     while (k < bp.K) {
         const lc_sources &s0 = srcs[k];
-        if (s0.kind != 0) {
+        if (s0.kind != 0 || bp.spec3d) {
+            // (3D spectra go through the plan's staging spectrum one slice at a time)
             int rc = push_impl(p, x, k, &s0);
             if (rc) return rc;
             ++k;
@@ -1282,8 +1289,7 @@ static int step_box(lc_plan_t *p, int x, const lc_sources *srcs, void *const *ou
                                       dcp, st));
             HIPCHK(launch_col_batch(n, p->t_f64, 1, true, spec, se, cnt, bp.tw_full, st));
         }
-        if (p->prec != LC_PREC_FP32 || bp.spec3d)
-            HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
+        if (p->prec != LC_PREC_FP32) HIPCHK(launch_col_batch(n, p->t_f64, 2, true, spec, se, cnt, bp.tw_full, st));
         for (int j = 0; j < cnt; ++j) bp.pushed[slot0 + j] = 1;
         k += cnt;
     }
@@ -1305,6 +1311,7 @@ static int step_impl(lc_plan_t *p, const lc_sources *srcs, void *const *out, int
             si[x] = a;
             oi[x] = o;
             for (int k = 0; k < p->boxes[x].K; ++k) dense = dense && srcs[a + k].kind == 0;
+            dense = dense && !p->boxes[x].spec3d;   // (the staging spectrum is shared)
             a += p->boxes[x].K;
             o += p->boxes[x].B;
         }

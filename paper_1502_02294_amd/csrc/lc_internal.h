@@ -95,6 +95,12 @@ hipError_t launch_x_inv(int n, bool t_f64, const void *spec, void *out, bool out
 hipError_t launch_col(int n, bool t_f64, int axis, bool fwd, void *spec, const void *tw_full,
                       hipStream_t st);
 
+// z forward pass of one FP32 spectrum `in` (y-transformed, whole-plane
+// layout) into `out` in the tile order of the slice-sum pass (3D spectra,
+// lc_schedule.spectra_3d): per column set, tiles of fused_cpw(n) columns
+// (the last narrower), each tile's N rows contiguous. in != out.
+hipError_t launch_col_z_tiled(int n, const void *in, void *out, const void *tw_full, hipStream_t st);
+
 // Plain multiply-accumulate A (+)= G^ S over one slice (first: A = G^ S).
 hipError_t launch_mac_plain(int n, bool t_f64, void *A, const void *S, const void *ghat, bool first,
                             hipStream_t st);
