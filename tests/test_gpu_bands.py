@@ -71,5 +71,20 @@ def test_bands_per_fused_launch_384(nbands, order):
                     d = np.sqrt(np.mean((Js[b] - ref2[b]) ** 2) / np.mean(ref2[b] ** 2))
                     print(f"  band={b} vs two-band launches: rel rms {d:.3e}", flush=True)
                     assert d <= 1e-5
+    # 3D spectra in the slice-sum pass's tile order (8-column tiles at 384):
+    # pushed again, then the product and sum alone, every bands-per-launch
+    # setting
+    plan.set_schedule(0, spectra_3d=1, fused_rounds=1)
+    keep += [plan.push_grid(0, k, torch.from_numpy(li.dense_grid(n, cells, lum, np.float32)).cuda())
+             for k, (cells, lum) in enumerate(box.sources)]
+    for fb in (nbands, 2):
+        print(f"case n={n} nbands={nbands} {order} spectra_3d fused_bands={fb}", flush=True)
+        plan.set_schedule(0, fused_bands=fb)
+        for b in range(nbands):
+            J = plan.field(0, b).double().cpu().numpy().ravel()
+            e_max, e_rms = oracle.rel_errors(J[tg], Jr[b])
+            d = np.sqrt(np.mean((J - ref2[b]) ** 2) / np.mean(ref2[b] ** 2))
+            print(f"  band={b} e_max={e_max:.3e} e_rms={e_rms:.3e} vs default {d:.3e}", flush=True)
+            assert e_rms <= 1e-5 and e_max <= 1e-4 and d <= 1e-5
     del keep
     plan.close()
