@@ -84,25 +84,32 @@ def check(J, Jr, form, label):
 @pytest.fixture(scope="module")
 def grid128_ref():
     b = li.grf_128c_24s().boxes[0]
-    say("grid128: oracle kernel and spectral route (library FFT)")
+    say("grid128: oracle kernel and spectral route with naive DFTs (Eqs. 12-13)")
     G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
-    S = [oracle.deposit(b.n, c, v) for c, v in b.sources]
-    J = oracle.field_fft(lambda k: G[k], lambda k: S[k], b.n_slices, b.n)
+    S = np.stack([oracle.deposit(b.n, c, v) for c, v in b.sources])
+    J = oracle.field_dft(G, S)
+    say("grid128: library-FFT route and route D at sampled cells (cross-checks)")
+    JF = oracle.field_fft(lambda k: G[k], lambda k: S[k], b.n_slices, b.n)
     targets = li.sample_cells(2024, b.n, 256)
     JD = oracle.field_direct(G, b.sources, targets)
-    return b, J, targets, JD
+    return b, J, targets, JD, JF
 
 
 def test_grid128_routes_agree(grid128_ref):
-    b, J, targets, JD = grid128_ref
+    """The three oracle routes agree: naive DFTs (the reference the GPU is held
+    to), the library FFT, and the circular convolution sum of Eq. 11 at
+    sampled cells."""
+    b, J, targets, JD, JF = grid128_ref
     e_max, _ = oracle.rel_errors(J.ravel()[targets], JD)
+    assert e_max <= 1e-12
+    e_max, _ = oracle.rel_errors(J.ravel(), JF.ravel())
     assert e_max <= 1e-12
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32", "fp32_plain"])
 def test_grid128_full_grid(grid128_ref, form):
     lc = _lc()
-    b, J, targets, JD = grid128_ref
+    b, J, targets, JD, _ = grid128_ref
     prec = {"fp64": lc.LC_PREC_FP64, "fp32": lc.LC_PREC_FP32, "fp32_plain": lc.LC_PREC_FP32_PLAIN}[form]
     say(f"case grid128 {form}")
     Jg = gpu_fields([b], prec, as_points=True)[0][0]
@@ -119,7 +126,7 @@ def test_grid128_mean_is_fp64_dc(grid128_ref, form):
     FP32 form keeps this bin in FP64, so its mean (FP64 output) is right to
     far below FP32 rounding; the plain FP32 form is held to FP32 rounding."""
     lc = _lc()
-    b, J, targets, JD = grid128_ref
+    b, J, targets, JD, _ = grid128_ref
     G = oracle.build_G(b.n, b.box, b.radii, b.supersample, b.bands[0])
     S = [oracle.deposit(b.n, c, v) for c, v in b.sources]
     mu = oracle.mean_field(G, np.stack(S))
