@@ -443,6 +443,21 @@ def rolling_leg(lc, torch, box, grids, steps):
                     best = (t, v)
             plan.set_schedule(0, xy_variant=best[1], spectra_3d=1)
         out = torch.empty((n,) * 3, dtype=torch.float32, device="cuda")
+        if mode == "spectra_3d":
+            # the fastest slice-sum schedule on 3D spectra (the plan-time
+            # autotuner tuned it on the default layout)
+            with torch.cuda.stream(plan.stream):
+                for k in range(K):
+                    plan.push_grid(0, k, grids[k])
+            torch.cuda.synchronize()
+            best = None
+            for v in range(plan.get_schedule(0)["n_fused"]):
+                for r in (1, 0):
+                    plan.set_schedule(0, fused_variant=v, fused_rounds=r)
+                    t = plan.time_kernel(lc.LC_KERNEL_FUSED_Z, 0, 3)
+                    if best is None or t < best[0]:
+                        best = (t, v, r)
+            plan.set_schedule(0, fused_variant=best[1], fused_rounds=best[2])
         st = plan.stream
         with torch.cuda.stream(st):
             for k in range(K):

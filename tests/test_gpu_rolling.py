@@ -89,8 +89,9 @@ def test_rolling_matches_oracle_and_fresh_plan(form, as_points):
 
 
 # (24: a fused tile of 64 columns, wider than the Nyquist set and than the
-# main set's last tile, so the tile order's narrower last tiles are used)
-@pytest.mark.parametrize("n,bands", [(24, 1), (32, 1), (48, 2), (128, 1)])
+# main set's last tile, so the tile order's narrower last tiles are used;
+# 256 and 512: the eight-element schedule with one slice prefetched)
+@pytest.mark.parametrize("n,bands", [(24, 1), (32, 1), (48, 2), (128, 1), (256, 1), (512, 1)])
 def test_rolling_with_3d_spectra(n, bands):
     """spectra_3d = 1: every push (lc_push_sources, lc_advance, lc_step)
     also transforms the slice along z, and a field is the product with G^
@@ -118,6 +119,9 @@ def test_rolling_with_3d_spectra(n, bands):
                 xv = 0
             p.set_schedule(0, spectra_3d=1, xy_variant=xv)
             assert p.get_schedule(0)["spectra_3d"] == 1
+            if n in (256, 512):
+                # eight elements per thread, prefetch depth 1
+                p.set_schedule(0, fused_variant={256: 3, 512: 1}[n])
         plans[s3] = p
     grids = [torch.from_numpy(li.dense_grid(n, c, v)).float().cuda() for c, v in bins]
     keep = []
