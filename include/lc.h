@@ -394,7 +394,10 @@ typedef enum {
  *                  time pushes one slice and sums all K). Needs a
  *                  whole-plane xy shape. 0 (default): the fused z pass
  *                  transforms every slice along z at each field. FP32 form
- *                  only (-1 in the other forms); not tuned
+ *                  only (-1 in the other forms); not tuned. The plan-time
+ *                  autotuner times the fused schedules on the default
+ *                  layout; with 3D spectra, time each fused_variant with
+ *                  lc_time_kernel(LC_KERNEL_FUSED_Z) to pick one
  *   n_xy, n_fused, n_fused_bands  (lc_get_schedule only) shapes compiled
  *                  for this N/form; n_fused_bands = min(B, 4 at N = 384,
  *                  512, else 2)
