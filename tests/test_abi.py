@@ -193,3 +193,11 @@ int main(void) {
     s = list(map(int, out[4].split()))
     assert s == [C.sizeof(lc.lc_sources), lc.lc_sources.grid.offset, lc.lc_sources.n.offset,
                  lc.lc_sources.lum.offset]
+
+
+def test_plain_c_caller_builds_against_the_header(tmp_path):
+    """tests/c_abi_example.c (the GPU test's C caller) compiles as C11 with
+    gcc against include/lc.h and links against the built liblc.so."""
+    from test_gpu_c_abi import build_example
+    exe = build_example(str(tmp_path))
+    assert os.path.exists(exe)
