@@ -8,11 +8,15 @@
  * Usage: c_abi_example <input> <output> <precision>
  *   input:  int32 n, int32 K, int32 m, double L, double radii[K+1], then per
  *           slice int64 count, int64 cells[count], double lum[count]
- *   output: the field, N^3 doubles in the grid layout of lc.h
+ *   output: two fields, N^3 doubles each in the grid layout of lc.h: first
+ *           from host point lists pushed slice by slice and lc_field into
+ *           host memory; then from one whole step (lc_step) over dense
+ *           device grids into device memory, replayed from its captured
+ *           HIP graph (the second of two steps)
  *   precision: an lc_precision value
- * Device memory (the workspace) comes from the HIP runtime; sources are
- * host point lists and the output a host buffer, so lc_field synchronises.
- * Exit status 0 on success; on failure the library's message is printed.
+ * Device memory (the workspace, the dense grids, the step's output) comes
+ * from the HIP runtime. Exit status 0 on success; on failure the library's
+ * message is printed.
  */
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
@@ -66,9 +70,15 @@ int main(int argc, char **argv) {
             fprintf(stderr, "bad sources of slice %d\n", k);
             return 2;
         }
+        for (int64_t i = 0; i < counts[k]; ++i)
+            if (cells[k][i] < 0 || cells[k][i] >= (int64_t)n * n * n) {
+                fprintf(stderr, "cell out of range in slice %d\n", k);
+                return 2;
+            }
     }
     fclose(in);
 
+    const size_t n3 = (size_t)n * n * n;
     lc_box_desc box = {0};
     box.n = n;
     box.n_slices = K;
@@ -80,6 +90,15 @@ int main(int argc, char **argv) {
     desc.n_boxes = 1;
     desc.precision = atoi(argv[3]);
     desc.boxes = &box;
+    desc.use_graph = 1;
+    /* a stream of its own (default priority): a graph cannot be captured on
+     * the legacy default stream */
+    hipStream_t stream = NULL;
+    if (hipStreamCreate(&stream) != hipSuccess) {
+        fprintf(stderr, "hipStreamCreate failed\n");
+        return 1;
+    }
+    desc.hip_stream = stream;
 
     const size_t bytes = lc_workspace_bytes(&desc);
     if (bytes == 0) return fail("lc_workspace_bytes", LC_EINVAL);
@@ -109,16 +128,59 @@ int main(int argc, char **argv) {
         if ((rc = lc_push_sources(plan, 0, k, &s))) return fail("lc_push_sources", rc);
     }
 
-    const size_t n3 = (size_t)n * n * n;
-    double *J = malloc(sizeof(double) * n3);
+    double *J = malloc(sizeof(double) * 2 * n3);
     if (!J) return 2;
     void *outs[1] = {J};
     if ((rc = lc_field(plan, 0, 0, outs, LC_F64, LC_MEM_HOST))) return fail("lc_field", rc);
+
+    /* the same sources as dense device grids (nearest-grid-point deposit on
+     * the host), then two whole steps: the first captures the graph, the
+     * second replays it */
+    const int grid_f64 = desc.precision == LC_PREC_FP64;
+    const size_t vsz = grid_f64 ? sizeof(double) : sizeof(float);
+    void *host_grid = calloc(n3, vsz), *dgrids = NULL, *dout = NULL;
+    lc_sources *srcs = calloc((size_t)K, sizeof(lc_sources));
+    if (!host_grid || !srcs) return 2;
+    if (hipMalloc(&dgrids, vsz * n3 * (size_t)K) != hipSuccess || hipMalloc(&dout, sizeof(double) * n3) != hipSuccess) {
+        fprintf(stderr, "hipMalloc of the step buffers failed\n");
+        return 1;
+    }
+    for (int k = 0; k < K; ++k) {
+        double *g64 = host_grid;
+        float *g32 = host_grid;
+        for (size_t c = 0; c < n3; ++c) {
+            if (grid_f64) g64[c] = 0.0;
+            else g32[c] = 0.0f;
+        }
+        for (int64_t i = 0; i < counts[k]; ++i) {
+            if (grid_f64) g64[cells[k][i]] += lums[k][i];
+            else g32[cells[k][i]] += (float)lums[k][i];
+        }
+        char *dst = (char *)dgrids + vsz * n3 * (size_t)k;
+        if (hipMemcpy(dst, host_grid, vsz * n3, hipMemcpyHostToDevice) != hipSuccess) return 1;
+        srcs[k].kind = 0;
+        srcs[k].dtype = grid_f64 ? LC_F64 : LC_F32;
+        srcs[k].mem = LC_MEM_DEVICE;
+        srcs[k].grid = dst;
+    }
+    void *douts[1] = {dout};
+    for (int rep = 0; rep < 2; ++rep)
+        if ((rc = lc_step(plan, srcs, douts, LC_F64))) return fail("lc_step", rc);
+    if (hipStreamSynchronize(stream) != hipSuccess ||
+        hipMemcpy(J + n3, dout, sizeof(double) * n3, hipMemcpyDeviceToHost) != hipSuccess) {
+        fprintf(stderr, "copying the step's field back failed\n");
+        return 1;
+    }
     lc_destroy(plan);
+    hipFree(dgrids);
+    hipFree(dout);
     hipFree(ws);
+    hipStreamDestroy(stream);
+    free(host_grid);
+    free(srcs);
 
     FILE *out = fopen(argv[2], "wb");
-    if (!out || fwrite(J, sizeof(double), n3, out) != n3) {
+    if (!out || fwrite(J, sizeof(double), 2 * n3, out) != 2 * n3) {
         perror(argv[2]);
         return 2;
     }

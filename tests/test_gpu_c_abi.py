@@ -1,8 +1,10 @@
 """The C ABI from a plain C program (tests/c_abi_example.c), with no Python
 in the process that calls the library: lc_workspace_bytes, lc_plan,
 lc_build_greens, lc_push_sources (host point lists) and lc_field (host
-output), then the field against the CPU FP64 oracle (route D, full grid):
-FP64 form e_max <= 1e-12, FP32 form e_rms <= 1e-5 and e_max <= 1e-4.
+output); then lc_step over dense device grids into device memory, captured
+in a HIP graph and replayed. Both fields against the CPU FP64 oracle
+(route D, full grid): FP64 form e_max <= 1e-12, FP32 form e_rms <= 1e-5 and
+e_max <= 1e-4.
 """
 import os
 import struct
@@ -54,13 +56,15 @@ def test_plain_c_caller_matches_oracle(tmp_path, form):
     print(f"case c_abi_example {form} n={box.n} K={box.n_slices} m=2", flush=True)
     r = subprocess.run([exe, inp, out, str(prec)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
+    n3 = box.n ** 3
     J = np.fromfile(out, dtype="<f8")
-    assert J.size == box.n ** 3
+    assert J.size == 2 * n3
     G = oracle.build_G(box.n, box.box, box.radii, box.supersample, box.bands[0])
-    Jr = oracle.field_direct(G, box.sources, np.arange(box.n ** 3))
-    e_max, e_rms = oracle.rel_errors(J, Jr)
-    print(f"  e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
-    if form == "fp64":
-        assert e_max <= 1e-12
-    else:
-        assert e_rms <= 1e-5 and e_max <= 1e-4
+    Jr = oracle.field_direct(G, box.sources, np.arange(n3))
+    for what, Jx in (("point lists + lc_field", J[:n3]), ("dense grids + lc_step replay", J[n3:])):
+        e_max, e_rms = oracle.rel_errors(Jx, Jr)
+        print(f"  {what}: e_max={e_max:.3e} e_rms={e_rms:.3e}", flush=True)
+        if form == "fp64":
+            assert e_max <= 1e-12
+        else:
+            assert e_rms <= 1e-5 and e_max <= 1e-4
