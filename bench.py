@@ -137,6 +137,21 @@ def timed_steps(torch, plan, grids, outs, steps, warmup):
     return e0.elapsed_time(e1) / steps, 1e3 * wall / steps
 
 
+def per_step_times(torch, plan, grids, outs, steps):
+    """Median and minimum of single steps, each bracketed by its own pair of
+    events on the plan's stream (after the timed region; not `value`)."""
+    st = plan.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    with torch.cuda.stream(st):
+        for a, b in ev:
+            a.record(st)
+            plan.step(grids, outs)
+            b.record(st)
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"median": t[len(t) // 2], "min": t[0], "count": steps}
+
+
 def run_form(lc, torch, boxes, grids, precision, steps, warmup, time_kernels=True):
     """Build, then time `steps` graph-replayed lc_step calls over all boxes."""
     fused = precision == lc.LC_PREC_FP32
@@ -151,6 +166,7 @@ def run_form(lc, torch, boxes, grids, precision, steps, warmup, time_kernels=Tru
     ms, wall_ms = timed_steps(torch, plan, grids, outs, steps, warmup)
     cells = sum(b.n ** 3 * b.n_slices for b in boxes)
     res = {"ms_per_step": ms, "wall_ms_per_step": wall_ms, "build_s": t_build,
+           "step_ms": per_step_times(torch, plan, grids, outs, steps),
            "value": cells / (ms * 1e-3), "schedule": plan.get_schedule(0)}
     if time_kernels:
         res["kernels"] = kernel_times(lc, plan, boxes[0], precision, ms)
@@ -553,6 +569,7 @@ def main():
     line = {
         "metric": METRIC, "value": r32["value"], "unit": "cell-slices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+        "step_ms": r32["step_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {desc}", "grid": n, "slices": K, "bands": B,
