@@ -137,6 +137,26 @@ def timed_steps(torch, plan, grids, outs, steps, warmup):
     return e0.elapsed_time(e1) / steps, 1e3 * wall / steps
 
 
+def copy_probe_gbps(torch, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of nbytes (the runtime's copy kernel),
+    bytes read plus bytes written per second: what a copy-like pass reaches
+    on this device."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def per_step_times(torch, plan, grids, outs, steps):
     """Median and minimum of single steps, each bracketed by its own pair of
     events on the plan's stream (after the timed region; not `value`)."""
@@ -606,6 +626,10 @@ def main():
                      "traffic": traffic.get(dom),
                      "traffic_over_pass": traffic[dom] / kd["pass_bytes"] if dom in traffic else None},
     }
+    probe = copy_probe_gbps(torch)
+    line["roofline"]["copy_probe_GBps"] = probe
+    line["roofline"]["pass_frac_of_copy_probe"] = line["roofline"]["pass_GBps"] / probe
+    line["roofline"]["dominant"]["pass_frac_of_copy_probe"] = kd["pass_GBps"] / probe
     line["kernels"] = {k: {"avg_ms": round(v["avg_ms"], 5), "pass_GBps": round(v["pass_GBps"], 1),
                            "step_share": round(v["step_share"], 3),
                            "slices_per_launch": v["slices_per_launch"],
