@@ -281,3 +281,36 @@ def test_rebuilt_kernel_recaptures_the_step():
         say(f"recapture prec={prec}: e_max={e_max:.3e} e_rms={e_rms:.3e}")
         assert (e_max <= 1e-12) if prec == lc.LC_PREC_FP64 else (e_rms <= 1e-5)
         plan.close()
+
+
+@pytest.mark.parametrize("form,s3", [("fp64", 0), ("fp32", 0), ("fp32", 1)])
+def test_rolling_through_several_ring_wraps(form, s3):
+    """23 observing times with K = 5 slices: the ring's head wraps four
+    times. Every fourth field (and the last) against the oracle's field for
+    the lookback-ordered sources, route D on the full grid; new slices
+    alternate between point lists and dense grids; FP32 forms with and
+    without 3D spectra."""
+    lc = _lc()
+    n, L, K, steps = 24, 18.0, 5, 23
+    radii = np.linspace(0.0, 16.0, K + 1)
+    bins = _bins(n, K + steps, 91)
+    box = li.Box(n=n, box=L, radii=radii, supersample=2, bands=[li.lw_band(14.0)], sources=_lookback(bins, K, 0))
+    G = oracle.build_G(n, L, radii, 2, box.bands[0])
+    f64 = form == "fp64"
+    p = lc.Plan([box], precision=lc.LC_PREC_FP64 if f64 else lc.LC_PREC_FP32)
+    p.build_all()
+    if s3:
+        p.set_schedule(0, spectra_3d=1, xy_variant=p.get_schedule(0)["xy_variant"])
+    keep = [_push(p, 0, k, s, False, f64) for k, s in enumerate(box.sources)]
+    for t in range(steps):
+        if t > 0:
+            keep.append(_advance(p, 0, bins[t + K - 1], t % 2 == 0, f64))
+        if t % 4 and t != steps - 1:
+            continue
+        J = p.field(0, 0).double().cpu().numpy().ravel()
+        Jr = oracle.field_direct(G, _lookback(bins, K, t), np.arange(n ** 3))
+        e_max, e_rms = oracle.rel_errors(J, Jr)
+        say(f"rolling wraps {form} spectra_3d={s3} t={t}: e_max={e_max:.3e} e_rms={e_rms:.3e}")
+        assert (e_max <= 1e-12) if f64 else (e_rms <= 1e-5 and e_max <= 1e-4)
+    p.close()
+    del keep
