@@ -21,7 +21,6 @@ roofline.dominant.
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
